@@ -1,0 +1,9 @@
+"""CPU oracle for the tactile readout — TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the package smoke check and the CPU-baseline leg of the
+benchmark import this package.  The product path (the HIP library and its
+binding) never does.  The oracle shares no code with the product: it has its
+own C source, its own structs and its own Python marshalling; the two meet only
+in the seeded scene generator, which holds no readout arithmetic.
+"""
+from .oracle import (Oracle, build, run_readout, philox4x32_10, bf16_round, dense_xtalk, u01)  # noqa: F401

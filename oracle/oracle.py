@@ -1,0 +1,209 @@
+"""ctypes marshalling for the C oracle (oracle.c).  TEST INFRASTRUCTURE ONLY."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle (contraction off, no fast-math, OpenMP)."""
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "oracle_impl.h", "oracle.h", "nsdf.c", "thermal.c")]
+    srcs = [s for s in srcs if os.path.exists(s)]
+    if not force and os.path.exists(_LIB) and all(os.path.getmtime(_LIB) >= os.path.getmtime(s) for s in srcs):
+        return _LIB
+    cfiles = [s for s in srcs if s.endswith(".c")]
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+                           "-shared", "-fPIC", "-o", tmp] + cfiles + ["-lm"])
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OrGrid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("origin", C.c_float * 3), ("spacing", C.c_float),
+                ("values", C.c_void_p), ("sphere_c", C.c_double * 3), ("sphere_r", C.c_double)]
+
+
+class OrProblem(C.Structure):
+    _fields_ = [("num_envs", C.c_int32), ("env_index", C.c_void_p),
+                ("num_links", C.c_int32), ("num_taxels", C.c_int32), ("num_objects", C.c_int32),
+                ("link_offset", C.c_void_p), ("taxel_pos", C.c_void_p), ("taxel_normal", C.c_void_p),
+                ("taxel_radius", C.c_void_p), ("grids", C.c_void_p),
+                ("k_n", C.c_float), ("c_n", C.c_float), ("alpha", C.c_float), ("k_t", C.c_float),
+                ("k_w", C.c_float), ("mu", C.c_float), ("prox_range", C.c_float), ("eta_on", C.c_float),
+                ("spring_only", C.c_int32), ("noise_on", C.c_int32), ("seed", C.c_uint64),
+                ("drift_sigma", C.c_float), ("white_sigma", C.c_float), ("bias", C.c_float),
+                ("quant_step", C.c_float), ("hyst_mode", C.c_int32), ("tau_load", C.c_float),
+                ("tau_unload", C.c_float), ("maxwell_beta", C.c_float), ("maxwell_tau", C.c_float),
+                ("dt", C.c_float), ("p_dead", C.c_float), ("stuck_lo", C.c_float), ("stuck_hi", C.c_float),
+                ("radius_rho", C.c_float), ("gain_lo", C.c_float), ("gain_hi", C.c_float),
+                ("xtalk_kind", C.c_int32), ("xtalk_chi", C.c_float), ("xtalk_sigma", C.c_float),
+                ("eta_off", C.c_float)]
+
+
+class OrInputs(C.Structure):
+    _fields_ = [("link_state", C.c_void_p), ("obj_id", C.c_void_p), ("obj_state", C.c_void_p),
+                ("step0", C.c_int64), ("num_steps", C.c_int32)]
+
+
+class OrOutputs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("bit", "bit_noisy", "depth", "prox", "surfdist", "ft", "ft_noisy",
+                                         "normal", "link_sums", "link_sums_noisy", "xtalk_scale")]
+
+
+class OrState(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("drift", "hyst", "hyst_prev", "schmitt", "dead", "stuck", "gain")]
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = C.CDLL(_LIB)
+        lib.or_philox4x32_10.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        for n in ("or_run_f32", "or_run_f64"):
+            getattr(lib, n).argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+            getattr(lib, n).restype = C.c_int
+        for n in ("or_reset_f32", "or_reset_f64"):
+            getattr(lib, n).argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]
+            getattr(lib, n).restype = C.c_int
+        lib.or_dense_xtalk_f64.argtypes = [C.c_void_p, C.c_void_p]
+        lib.or_bf16_round.argtypes = [C.c_float]
+        lib.or_bf16_round.restype = C.c_float
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    lib = _load()
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    o = np.zeros(4, dtype=np.uint32)
+    lib.or_philox4x32_10(c.ctypes.data, k.ctypes.data, o.ctypes.data)
+    return o
+
+
+def u01(x):
+    x = np.asarray(x, dtype=np.uint64)
+    return (2 * (x >> 9) + 1).astype(np.float64) * 2.0 ** -24
+
+
+def bf16_round(x: float) -> float:
+    return float(_load().or_bf16_round(float(x)))
+
+
+class Oracle:
+    """Holds one marshalled problem (a scene restricted to a set of envs) and its noise state."""
+
+    def __init__(self, scene, envs: Optional[np.ndarray] = None, precision: str = "f32",
+                 grids_override=None):
+        self.lib = _load()
+        self.sc = scene
+        self.prec = precision
+        lay = scene.layout
+        self.E = scene.num_envs if envs is None else len(envs)
+        self.T, self.L = lay.num_taxels, lay.num_links
+        self.env_index = (np.arange(self.E, dtype=np.int32) if envs is None
+                          else np.ascontiguousarray(envs, dtype=np.int32))
+        self._keep = []
+        grids = grids_override if grids_override is not None else scene.grids
+        garr = (OrGrid * max(1, len(grids)))()
+        for i, g in enumerate(grids):
+            if isinstance(g, dict):          # analytic sphere (pins)
+                garr[i].n = 0
+                garr[i].sphere_c[:] = list(g["c"])
+                garr[i].sphere_r = g["r"]
+                continue
+            v = np.ascontiguousarray(g.values, dtype=np.float32)
+            self._keep.append(v)
+            garr[i].n = g.n
+            garr[i].origin[:] = [float(x) for x in g.origin]
+            garr[i].spacing = float(g.spacing)
+            garr[i].values = v.ctypes.data
+        self._keep.append(garr)
+        self.arrs = dict(off=np.ascontiguousarray(lay.link_offset, dtype=np.int32),
+                         pos=np.ascontiguousarray(lay.pos, dtype=np.float32),
+                         nrm=np.ascontiguousarray(lay.normal, dtype=np.float32),
+                         rad=np.ascontiguousarray(lay.radius, dtype=np.float32))
+        f, nz = scene.force, scene.noise
+        P = OrProblem()
+        P.num_envs, P.env_index = self.E, self.env_index.ctypes.data
+        P.num_links, P.num_taxels, P.num_objects = self.L, self.T, len(grids)
+        P.link_offset, P.taxel_pos = self.arrs["off"].ctypes.data, self.arrs["pos"].ctypes.data
+        P.taxel_normal, P.taxel_radius = self.arrs["nrm"].ctypes.data, self.arrs["rad"].ctypes.data
+        P.grids = C.addressof(garr)
+        P.k_n, P.c_n, P.alpha, P.k_t, P.k_w, P.mu = f.k_n, f.c_n, f.alpha, f.k_t, f.k_w, f.mu
+        P.prox_range, P.eta_on, P.spring_only = f.prox_range, f.eta_on, int(f.spring_only)
+        P.noise_on, P.seed = int(nz.enabled), nz.seed
+        P.drift_sigma, P.white_sigma, P.bias, P.quant_step = nz.drift_sigma, nz.white_sigma, nz.bias, nz.quant_step
+        P.hyst_mode, P.tau_load, P.tau_unload = nz.hyst_mode, nz.tau_load_steps, nz.tau_unload_steps
+        P.maxwell_beta, P.maxwell_tau, P.dt = nz.maxwell_beta, nz.maxwell_tau_s, nz.dt_s
+        P.p_dead, P.stuck_lo, P.stuck_hi = nz.p_dead, nz.stuck_lo, nz.stuck_hi
+        P.radius_rho, P.gain_lo, P.gain_hi = nz.radius_rho, nz.gain_lo, nz.gain_hi
+        P.xtalk_kind, P.xtalk_chi, P.xtalk_sigma, P.eta_off = nz.xtalk_kind, nz.xtalk_chi, nz.xtalk_sigma, nz.eta_off
+        self.P = P
+        E, T = self.E, self.T
+        self.state = dict(drift=np.zeros((6, E, T)), hyst=np.zeros((6, E, T)), hyst_prev=np.zeros((6, E, T)),
+                          schmitt=np.zeros((E, T), np.uint8), dead=np.zeros((E, T), np.uint8),
+                          stuck=np.zeros((E, T)), gain=np.ones((E, T)))
+        self.St = OrState(**{k: v.ctypes.data for k, v in self.state.items()})
+        self.reset(None, 0)
+
+    def reset(self, env_mask: Optional[np.ndarray], step: int):
+        m = None if env_mask is None else np.ascontiguousarray(env_mask, dtype=np.uint8)
+        fn = self.lib.or_reset_f32 if self.prec == "f32" else self.lib.or_reset_f64
+        fn(C.byref(self.P), C.byref(self.St), _ptr(m), int(step))
+
+    def run(self, inp, threads: int = 0, want=("bit", "bit_noisy", "depth", "prox", "surfdist", "ft", "ft_noisy",
+                                                "normal", "link_sums", "link_sums_noisy", "xtalk_scale")) -> Dict[str, np.ndarray]:
+        S = inp.link_state.shape[0]
+        E, T, L = self.E, self.T, self.L
+        ls = np.ascontiguousarray(inp.link_state, dtype=np.float32)
+        oid = np.ascontiguousarray(inp.obj_id, dtype=np.int32)
+        ost = None if inp.obj_state is None else np.ascontiguousarray(inp.obj_state, dtype=np.float32)
+        assert ls.shape == (S, 13, E * L) and oid.shape == (S, E)
+        shapes = dict(bit=((S, E, T), np.uint8), bit_noisy=((S, E, T), np.uint8), depth=((S, E, T), np.float64),
+                      prox=((S, E, T), np.float64), surfdist=((S, E, T), np.float64),
+                      ft=((S, 6, E, T), np.float64), ft_noisy=((S, 6, E, T), np.float64),
+                      normal=((S, 3, E, T), np.float64), link_sums=((S, 11, E, L), np.float64),
+                      link_sums_noisy=((S, 11, E, L), np.float64), xtalk_scale=((S, 6, E, T), np.float64))
+        out = {k: np.zeros(*shapes[k]) for k in want}
+        O = OrOutputs(**{k: v.ctypes.data for k, v in out.items()})
+        I = OrInputs(ls.ctypes.data, oid.ctypes.data, _ptr(ost), int(inp.step0), S)
+        fn = self.lib.or_run_f32 if self.prec == "f32" else self.lib.or_run_f64
+        rc = fn(C.byref(self.P), C.byref(I), C.byref(O), C.byref(self.St), int(threads or os.cpu_count() or 1))
+        assert rc == 0
+        return out
+
+
+def run_readout(scene, inp, envs=None, precision="f32", threads=0, **kw):
+    """Convenience: fresh oracle (reset at inp.step0) over `envs`, run every step of `inp`."""
+    o = Oracle(scene, envs, precision)
+    o.reset(None, inp.step0)
+    return o.run(inp, threads=threads, **kw)
+
+
+def dense_xtalk(scene) -> list:
+    """The FP64 per-link crosstalk blocks the oracle uses (row-major, one per link)."""
+    o = Oracle(scene, np.arange(1), "f64")
+    lay = scene.layout
+    n = np.diff(lay.link_offset)
+    buf = np.zeros(int((n * n).sum()))
+    o.lib.or_dense_xtalk_f64(C.byref(o.P), buf.ctypes.data)
+    out, off = [], 0
+    for k in n:
+        out.append(buf[off:off + k * k].reshape(k, k).copy())
+        off += k * k
+    return out

@@ -1,0 +1,440 @@
+"""Seeded synthetic scenes shaped like the paper's tactile workloads.
+
+This module is input generation only.  It builds taxel layouts, object SDF
+grids and link trajectories in FP64 with numpy, rounds them once to FP32, and
+hands them to whoever asks (the HIP path and the CPU oracle alike).  It does
+none of the readout arithmetic: no pose transform of taxels, no grid lookup,
+no force law, no noise.
+
+Shapes follow the paper: probes on planar patches rigidly attached to links
+(App. A.1), hand layouts sized like the probe-count table (App. B, "Tactile
+Placement and Probe Counts"), and objects like the cube/cylinder sets used in
+training (App. B, tasks).  The paper's assets are not available, so primitive
+and convex-hull objects stand in for them.
+
+Configurations (sizes, seeds):
+  c1  64 envs x 5 links x 20 taxels, one 3 cm sphere on a 32^3 grid, random
+      poses within 4 cm of the centre, 10 steps, noise off.
+  c2  4096 envs x 16 links (uneven 8..40 taxels, 200 total), 8 objects on 64^3
+      grids, sinusoidal trajectories, 100 steps, drift + lag + dead + banded
+      crosstalk.
+  c3  20480 envs x 16 links (16..128 taxels, 1024 total), 32 objects, 64
+      steps, dense crosstalk.
+  c4  the c3 hand with 256 objects, 16 steps, noise off (neural-SDF workload).
+  c5  the c2 hand at dt = 1 ms for 500 steps (thermal workload).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field, replace
+from typing import List, Optional
+
+import numpy as np
+
+MASTER_SEED = 260622332
+PITCH = 2.0e-3          # taxel pitch on every patch [m]
+TAXEL_RADIUS = 1.0e-3   # probe radius R_j [m]
+FAMILIES = ["sphere", "box", "capsule", "torus", "hull", "box", "capsule", "hull"]
+
+C2_LINKS = [40, 20, 16, 16, 16, 12] + [8] * 10
+C3_LINKS = [128, 117, 101, 93, 85, 71, 66, 60, 54, 49, 43, 37, 32, 29, 25, 34]
+
+
+# ----------------------------------------------------------------------------------------------
+# data containers
+# ----------------------------------------------------------------------------------------------
+@dataclass
+class Layout:
+    """Taxels of one robot, shared by every env; taxels are sorted by link."""
+    link_offset: np.ndarray   # int32 [L+1]
+    pos: np.ndarray           # float32 [T,3] link-frame centre x_j
+    normal: np.ndarray        # float32 [T,3] link-frame unit normal n_j
+    radius: np.ndarray        # float32 [T]   R_j (0 = inactive filler)
+
+    @property
+    def num_links(self) -> int:
+        return int(self.link_offset.shape[0] - 1)
+
+    @property
+    def num_taxels(self) -> int:
+        return int(self.pos.shape[0])
+
+    def link_of_taxel(self) -> np.ndarray:
+        return np.repeat(np.arange(self.num_links, dtype=np.int32), np.diff(self.link_offset))
+
+
+@dataclass
+class Grid:
+    """Node-centred SDF grid in the object frame: N nodes per axis over [o, o+(N-1)h]."""
+    n: int
+    origin: np.ndarray        # float32 [3]
+    spacing: np.float32
+    values: np.ndarray        # float32 [N,N,N] indexed [z,y,x] (x fastest in memory)
+    family: str = ""
+    shape: dict = field(default_factory=dict)
+
+
+@dataclass
+class ForceParams:
+    k_n: float = 2000.0
+    c_n: float = 5.0
+    alpha: float = 1.0
+    k_t: float = 2.0
+    k_w: float = 2.0
+    mu: float = 0.8
+    prox_range: float = 0.01
+    eta_on: float = 5.0e-4
+    spring_only: bool = False
+
+
+@dataclass
+class NoiseParams:
+    enabled: bool = False
+    seed: int = 0
+    drift_sigma: float = 0.0
+    white_sigma: float = 0.0
+    bias: float = 0.0
+    quant_step: float = 0.0
+    hyst_mode: int = 0            # 0 off, 1 asymmetric first-order lag, 2 Maxwell element
+    tau_load_steps: float = 0.0
+    tau_unload_steps: float = 0.0
+    maxwell_beta: float = 0.0
+    maxwell_tau_s: float = 0.0
+    dt_s: float = 0.005
+    p_dead: float = 0.0
+    stuck_lo: float = 0.0
+    stuck_hi: float = 0.0
+    radius_rho: float = 0.0
+    gain_lo: float = 1.0
+    gain_hi: float = 1.0
+    xtalk_kind: int = 0           # 0 none, 1 banded, 2 dense per-link matrix
+    xtalk_chi: float = 0.0
+    xtalk_sigma: float = 0.0
+    eta_off: float = 5.0e-4
+
+
+@dataclass
+class Scene:
+    name: str
+    num_envs: int
+    num_steps: int
+    layout: Layout
+    grids: List[Grid]
+    force: ForceParams
+    noise: NoiseParams
+    dt: float = 0.005
+    geom_seed: int = MASTER_SEED
+
+
+@dataclass
+class Inputs:
+    """Per-step device-shaped inputs (host copies)."""
+    link_state: np.ndarray            # float32 [S,13,E*L]: p(3) q=(w,x,y,z)(4) v(3) omega(3)
+    obj_id: np.ndarray                # int32 [S,E]
+    obj_state: Optional[np.ndarray]   # float32 [S,13,E] or None (object static at the env origin)
+    step0: int = 0
+
+
+# ----------------------------------------------------------------------------------------------
+# layouts
+# ----------------------------------------------------------------------------------------------
+def patch(n: int, pitch: float = PITCH) -> np.ndarray:
+    """n taxel centres on a near-square grid at `pitch` in the link z=0 plane; last row partial."""
+    cols = int(math.ceil(math.sqrt(n)))
+    rows = int(math.ceil(n / cols))
+    pts = []
+    for r in range(rows):
+        for c in range(cols):
+            if len(pts) == n:
+                break
+            pts.append(((c - (cols - 1) / 2.0) * pitch, (r - (rows - 1) / 2.0) * pitch, 0.0))
+    return np.asarray(pts, dtype=np.float64)
+
+
+def make_layout(counts: List[int], radius: float = TAXEL_RADIUS) -> Layout:
+    pos = np.concatenate([patch(n) for n in counts], axis=0)
+    T = pos.shape[0]
+    normal = np.zeros((T, 3)); normal[:, 2] = 1.0
+    off = np.zeros(len(counts) + 1, dtype=np.int32)
+    off[1:] = np.cumsum(counts)
+    return Layout(off, pos.astype(np.float32), normal.astype(np.float32),
+                  np.full(T, radius, dtype=np.float32))
+
+
+# ----------------------------------------------------------------------------------------------
+# object shapes (FP64 analytic signed distances, used only to fill grids and place trajectories)
+# ----------------------------------------------------------------------------------------------
+_hull_lib = None
+
+
+def _load_hull_lib():
+    global _hull_lib
+    if _hull_lib is None:
+        path = os.path.join(os.path.dirname(__file__), "_synth_hull.so")
+        if not os.path.exists(path):
+            build_hull_lib()
+        lib = ctypes.CDLL(path)
+        lib.hull_sdf_points.restype = None
+        lib.hull_sdf_points.argtypes = [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _hull_lib = lib
+    return _hull_lib
+
+
+def build_hull_lib() -> str:
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    src = os.path.join(here, "synth_hull.c")
+    out = os.path.join(here, "_synth_hull.so")
+    subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", out, src, "-lm"])
+    return out
+
+
+def make_shape(family: str, extent: float, rng: np.random.Generator) -> dict:
+    s = {"family": family, "extent": extent}
+    if family == "sphere":
+        s["r"] = extent / 2
+    elif family == "box":
+        a = rng.uniform(0.5, 1.0, size=2)
+        s["b"] = np.array([extent / 2, extent / 2 * a[0], extent / 2 * a[1]])
+    elif family == "capsule":
+        r = extent * rng.uniform(1 / 6, 1 / 4)
+        s["r"] = r
+        s["hl"] = extent / 2 - r
+    elif family == "torus":
+        s["R"] = extent * 3 / 8
+        s["r"] = extent / 8
+    elif family == "hull":
+        from scipy.spatial import ConvexHull
+        d = rng.normal(size=(32, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        scale = np.array([1.0, rng.uniform(0.6, 1.0), rng.uniform(0.6, 1.0)]) * extent / 2
+        v = d * scale
+        h = ConvexHull(v)
+        planes = h.equations.copy()          # a.x + b.y + c.z + d <= 0 inside; normals unit
+        s["verts"] = v
+        s["tris"] = h.simplices.astype(np.int32)
+        s["planes"] = np.concatenate([planes[:, :3], -planes[:, 3:4]], axis=1)  # n.x - off
+    else:
+        raise ValueError(family)
+    return s
+
+
+def shape_sdf(s: dict, p: np.ndarray) -> np.ndarray:
+    """Exact FP64 signed distance of shape `s` at points p [...,3] (object frame)."""
+    p = np.asarray(p, dtype=np.float64)
+    f = s["family"]
+    if f == "sphere":
+        return np.linalg.norm(p, axis=-1) - s["r"]
+    if f == "box":
+        q = np.abs(p) - s["b"]
+        return np.linalg.norm(np.maximum(q, 0), axis=-1) + np.minimum(q.max(axis=-1), 0)
+    if f == "capsule":
+        z = np.clip(p[..., 2], -s["hl"], s["hl"])
+        d = p.copy(); d[..., 2] -= z
+        return np.linalg.norm(d, axis=-1) - s["r"]
+    if f == "torus":
+        qx = np.hypot(p[..., 0], p[..., 1]) - s["R"]
+        return np.hypot(qx, p[..., 2]) - s["r"]
+    if f == "hull":
+        lib = _load_hull_lib()
+        flat = np.ascontiguousarray(p.reshape(-1, 3))
+        out = np.empty(flat.shape[0])
+        v = np.ascontiguousarray(s["verts"]); t = np.ascontiguousarray(s["tris"])
+        pl = np.ascontiguousarray(s["planes"])
+        lib.hull_sdf_points(flat.shape[0], flat.ctypes.data, v.shape[0], v.ctypes.data, t.shape[0],
+                            t.ctypes.data, pl.ctypes.data, out.ctypes.data)
+        return out.reshape(p.shape[:-1])
+    raise ValueError(f)
+
+
+def shape_grad(s: dict, p: np.ndarray, h: float = 1e-6) -> np.ndarray:
+    g = np.zeros(p.shape)
+    for k in range(3):
+        e = np.zeros(3); e[k] = h
+        g[..., k] = (shape_sdf(s, p + e) - shape_sdf(s, p - e)) / (2 * h)
+    return g
+
+
+def sample_grid(s: dict, n: int, side: float) -> Grid:
+    o = -side / 2
+    h = side / (n - 1)
+    ax = o + h * np.arange(n)
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    P = np.stack([X, Y, Z], axis=-1)
+    vals = shape_sdf(s, P).astype(np.float32)
+    return Grid(n, np.full(3, o, dtype=np.float32), np.float32(h), np.ascontiguousarray(vals),
+                s["family"], s)
+
+
+def make_objects(n_obj: int, rng: np.random.Generator, n: int = 64, margin: float = 0.04) -> List[Grid]:
+    grids = []
+    for k in range(n_obj):
+        fam = FAMILIES[k % len(FAMILIES)]
+        extent = rng.uniform(0.02, 0.06)
+        s = make_shape(fam, extent, rng)
+        grids.append(sample_grid(s, n, extent + margin))
+    return grids
+
+
+# ----------------------------------------------------------------------------------------------
+# rotations (input generation only)
+# ----------------------------------------------------------------------------------------------
+def quat_mul(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    w1, x1, y1, z1 = np.moveaxis(a, -1, 0)
+    w2, x2, y2, z2 = np.moveaxis(b, -1, 0)
+    return np.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2,
+                     w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2,
+                     w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2], axis=-1)
+
+
+def matrix_to_quat(R: np.ndarray) -> np.ndarray:
+    from scipy.spatial.transform import Rotation
+    xyzw = Rotation.from_matrix(R.reshape(-1, 3, 3)).as_quat()
+    q = np.concatenate([xyzw[:, 3:4], xyzw[:, :3]], axis=1)
+    return q.reshape(R.shape[:-2] + (4,))
+
+
+def random_unit(rng: np.random.Generator, n: int) -> np.ndarray:
+    d = rng.normal(size=(n, 3))
+    return d / np.linalg.norm(d, axis=1, keepdims=True)
+
+
+# ----------------------------------------------------------------------------------------------
+# configurations
+# ----------------------------------------------------------------------------------------------
+def c2_noise(seed: int) -> NoiseParams:
+    return NoiseParams(enabled=True, seed=seed, drift_sigma=1e-3, hyst_mode=1, tau_load_steps=2.0,
+                       tau_unload_steps=6.0, p_dead=0.02, xtalk_kind=1, xtalk_chi=0.05, eta_off=2e-4)
+
+
+def make_scene(cfg: str, num_envs: Optional[int] = None, num_steps: Optional[int] = None) -> Scene:
+    k = int(cfg[1])
+    rng = np.random.default_rng(MASTER_SEED + k)
+    key = MASTER_SEED + 100 * k
+    if cfg == "c1":
+        layout = make_layout([20] * 5)
+        s = {"family": "sphere", "extent": 0.06, "r": 0.03}
+        grids = [sample_grid(s, 32, 0.10)]
+        sc = Scene("c1", 64, 10, layout, grids, ForceParams(), NoiseParams(seed=key))
+    elif cfg == "c2":
+        layout = make_layout(C2_LINKS)
+        sc = Scene("c2", 4096, 100, layout, make_objects(8, rng), ForceParams(), c2_noise(key))
+    elif cfg == "c3":
+        layout = make_layout(C3_LINKS)
+        nz = c2_noise(key)
+        nz.xtalk_kind, nz.xtalk_chi, nz.xtalk_sigma = 2, 0.1, 2e-3
+        sc = Scene("c3", 20480, 64, layout, make_objects(32, rng), ForceParams(), nz)
+    elif cfg == "c4":
+        layout = make_layout(C3_LINKS)
+        sc = Scene("c4", 20480, 16, layout, make_objects(256, rng), ForceParams(), NoiseParams(seed=key))
+    elif cfg == "c5":
+        layout = make_layout(C2_LINKS)
+        sc = Scene("c5", 4096, 500, layout, make_objects(8, rng), ForceParams(), c2_noise(key), dt=0.001)
+        sc.noise.dt_s = 0.001
+    else:
+        raise ValueError(cfg)
+    sc.geom_seed = MASTER_SEED + k
+    if num_envs is not None:
+        sc.num_envs = num_envs
+    if num_steps is not None:
+        sc.num_steps = num_steps
+    return sc
+
+
+def make_inputs(sc: Scene, num_steps: Optional[int] = None, step0: int = 0) -> Inputs:
+    """Trajectories for every env and link.  Random draws depend on (config seed, env count)."""
+    S = sc.num_steps if num_steps is None else num_steps
+    E, L = sc.num_envs, sc.layout.num_links
+    rng = np.random.default_rng(sc.geom_seed + 7919)
+    n_obj = len(sc.grids)
+    obj = rng.integers(0, n_obj, size=E).astype(np.int32)
+    link_state = np.empty((S, 13, E * L), dtype=np.float32)
+    if sc.name == "c1":
+        # independent uniform poses in a 4 cm ball around the sphere centre, every step
+        for t in range(S):
+            r = 0.04 * rng.uniform(size=E * L) ** (1 / 3)
+            p = random_unit(rng, E * L) * r[:, None]
+            q = rng.normal(size=(E * L, 4)); q /= np.linalg.norm(q, axis=1, keepdims=True)
+            v = rng.normal(0, 0.05, size=(E * L, 3))
+            w = rng.normal(0, 0.05, size=(E * L, 3))
+            link_state[t] = np.concatenate([p, q, v, w], axis=1).T.astype(np.float32)
+        return Inputs(link_state, np.repeat(obj[None], S, axis=0), None, step0)
+
+    # smooth sinusoidal trajectories around a base pose near the object surface
+    EL = E * L
+    env_obj = np.repeat(obj, L)
+    base_p = np.empty((EL, 3)); base_n = np.empty((EL, 3))
+    for g in range(n_obj):
+        idx = np.nonzero(env_obj == g)[0]
+        if idx.size == 0:
+            continue
+        s = sc.grids[g].shape
+        x = random_unit(rng, idx.size) * s["extent"]
+        for _ in range(3):   # project onto the surface along the exact SDF gradient
+            d = shape_sdf(s, x)
+            gr = shape_grad(s, x)
+            gr /= np.maximum(np.linalg.norm(gr, axis=1, keepdims=True), 1e-12)
+            x = x - d[:, None] * gr
+        base_p[idx] = x
+        base_n[idx] = gr
+    off = rng.uniform(-3e-3, 8e-3, size=EL)
+    c = base_p + off[:, None] * base_n
+    zax = -base_n
+    tmp = random_unit(rng, EL)
+    xax = tmp - (tmp * zax).sum(1, keepdims=True) * zax
+    xax /= np.linalg.norm(xax, axis=1, keepdims=True)
+    yax = np.cross(zax, xax)
+    Rb = np.stack([xax, yax, zax], axis=2)          # columns = link axes in the world
+    qb = matrix_to_quat(Rb)
+    A = rng.uniform(0, 5e-3, size=(EL, 3))
+    f = rng.uniform(0.5, 3.0, size=(EL, 3))
+    ph = rng.uniform(0, 2 * np.pi, size=(EL, 3))
+    ax = random_unit(rng, EL)
+    fr = rng.uniform(0.5, 3.0, size=EL)
+    phr = rng.uniform(0, 2 * np.pi, size=EL)
+    ax_w = np.einsum("nij,nj->ni", Rb, ax)
+    for t in range(S):
+        tt = (step0 + t) * sc.dt
+        arg = 2 * np.pi * f * tt + ph
+        p = c + A * np.sin(arg)
+        v = A * 2 * np.pi * f * np.cos(arg)
+        th = 0.3 * np.sin(2 * np.pi * fr * tt + phr)
+        thd = 0.3 * 2 * np.pi * fr * np.cos(2 * np.pi * fr * tt + phr)
+        qa = np.concatenate([np.cos(th / 2)[:, None], np.sin(th / 2)[:, None] * ax], axis=1)
+        q = quat_mul(qb, qa)
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        w = ax_w * thd[:, None]
+        link_state[t, 0:3] = p.T
+        link_state[t, 3:7] = q.T
+        link_state[t, 7:10] = v.T
+        link_state[t, 10:13] = w.T
+    return Inputs(link_state, np.repeat(obj[None], S, axis=0), None, step0)
+
+
+def random_object_state(sc: Scene, S: int, rng_seed: int = 1) -> np.ndarray:
+    """Optional moving-object inputs [S,13,E] (pose near the origin, small velocities)."""
+    rng = np.random.default_rng(rng_seed)
+    E = sc.num_envs
+    out = np.empty((S, 13, E), dtype=np.float32)
+    for t in range(S):
+        p = rng.normal(0, 2e-3, size=(E, 3))
+        q = rng.normal(size=(E, 4)); q[:, 0] += 6.0
+        q /= np.linalg.norm(q, axis=1, keepdims=True)
+        v = rng.normal(0, 0.05, size=(E, 3))
+        w = rng.normal(0, 0.5, size=(E, 3))
+        out[t] = np.concatenate([p, q, v, w], axis=1).T
+    return out
+
+
+def subset_envs(inp: Inputs, envs: np.ndarray, L: int) -> Inputs:
+    """Inputs restricted to the env indices `envs` (for sampled oracle checks)."""
+    envs = np.asarray(envs)
+    cols = (envs[:, None] * L + np.arange(L)[None, :]).reshape(-1)
+    ls = np.ascontiguousarray(inp.link_state[:, :, cols])
+    oid = np.ascontiguousarray(inp.obj_id[:, envs])
+    os_ = None if inp.obj_state is None else np.ascontiguousarray(inp.obj_state[:, :, envs])
+    return Inputs(ls, oid, os_, inp.step0)
