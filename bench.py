@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Throughput of the tactile readout on one MI355X.
+
+A "step" here is one pass of the whole hot path over one batch: a 64-step rollout of the
+20480-env x 1024-taxel hand (16 links of 16..128 taxels) against 32 objects on 64^3 grid SDFs,
+with the clean readout (contact bits, depth, proximity, force/torque), the noise model (dense
+BF16 crosstalk on MFMA, first-order lag, Gaussian drift, dead taxels, Schmitt bits) and the
+per-link sums, all in one persistent launch.  Inputs are resident in HBM before timing.
+
+Prints one JSON line with the throughput, the roofline of the readout kernel (algorithmic bytes
+per launch / measured launch time) and a CPU baseline (the oracle on a bounded sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "taxel-readouts/sec on 1 MI355X (grid-SDF vs neural-SDF at ≤0.5 mm depth err)"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(E, L, T, S, n_obj, grid_n, noisy=True, sums=True):
+    """Bytes the method must move for one launch of S steps (per readout: outputs, amortised
+    state, inputs, link sums; per launch: the grids once)."""
+    R = E * T * S
+    per_readout = 4 + 24 + 4 + 1 / 8                    # depth, f/tau, prox, clean bit
+    if noisy:
+        per_readout += 24 + 1 / 8                       # noisy f/tau, noisy bit
+    state = E * T * (2 * (24 + 24) + 2 * 1 / 8 + 1 / 8) if noisy else 0   # drift+lag r/w, Schmitt r/w, dead r
+    inputs = S * (E * L * 52 + E * 4)                   # link_state + obj_id
+    link = S * E * L * 44 * (2 if noisy else 1) if sums else 0
+    grids = n_obj * grid_n ** 3 * 4
+    return R * per_readout + state + inputs + link + grids, R
+
+
+def cpu_baseline(sc, inp, target_s=12.0):
+    """The oracle as it stands (FP32 parity build, OpenMP over envs) on a bounded sample of
+    envs of the same workload, all steps; scaled to readouts/s."""
+    import oracle
+    from paper_2606_22332_amd import synth
+    threads = os.cpu_count() or 1
+    L, T = sc.layout.num_links, sc.layout.num_taxels
+    n = max(threads, 8)
+    t0 = time.perf_counter()
+    envs = np.arange(n)
+    oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision="f32", threads=threads,
+                       want=("bit", "bit_noisy", "depth", "prox", "ft", "ft_noisy", "link_sums", "link_sums_noisy"))
+    dt = time.perf_counter() - t0
+    if dt < target_s / 4:
+        n2 = int(min(sc.num_envs, max(n, n * target_s / max(dt, 1e-3))))
+        envs = np.linspace(0, sc.num_envs - 1, n2).astype(np.int64)
+        t0 = time.perf_counter()
+        oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision="f32", threads=threads,
+                           want=("bit", "bit_noisy", "depth", "prox", "ft", "ft_noisy", "link_sums",
+                                 "link_sums_noisy"))
+        dt = time.perf_counter() - t0
+        n = n2
+    S = inp.link_state.shape[0]
+    return {"value": n * T * S / dt, "unit": "taxel-readouts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} of {sc.num_envs} envs x {T} taxels x {S} steps ({dt:.1f} s, FP32 oracle)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c3")
+    ap.add_argument("--envs", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+              "(environments shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+
+    sc = synth.make_scene(args.config, num_envs=args.envs)
+    t0 = time.perf_counter()
+    inp = synth.make_inputs(sc)
+    gen_s = time.perf_counter() - t0
+    E, L, T, S = sc.num_envs, sc.layout.num_links, sc.layout.num_taxels, inp.link_state.shape[0]
+    mask = B.TG_OUT_BITS | B.TG_OUT_DEPTH | B.TG_OUT_PROX | B.TG_OUT_FT | B.TG_OUT_LINK_SUMS
+    if sc.noise.enabled:
+        mask |= B.TG_OUT_NOISY
+    ro = B.Readout(sc, mask)
+    dinp = B.to_device(inp)
+    ro.alloc_outputs(S)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    # rollouts continue one another (the step counter advances by S each time), as in a long
+    # simulation; the noise state carries over on the device
+    step = 0
+    for _ in range(args.warmup):
+        dinp.step0 = step
+        ro.rollout(dinp, S)
+        step += S
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter()
+    for i in range(args.steps):
+        dinp.step0 = step
+        ev[i][0].record(stream)
+        ro.rollout(dinp, S)
+        ev[i][1].record(stream)
+        step += S
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_wall
+    kernel_ms = [a.elapsed_time(b) for a, b in ev]
+    ms = float(np.mean(kernel_ms))
+    readouts = E * T * S
+    value = readouts / (wall / args.steps)
+    nbytes, _ = algorithmic_bytes(E, L, T, S, len(sc.grids), sc.grids[0].n, sc.noise.enabled, True)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    eb, threads = ro.launch_shape()
+    rec = {
+        "metric": METRIC, "value": value, "unit": "taxel-readouts/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{sc.name}: {E} envs x {T} taxels ({L} links) x {S}-step rollout, grid SDF "
+                               f"({len(sc.grids)} objects, {sc.grids[0].n}^3), "
+                               + ("noisy, " + {0: "no", 1: "banded", 2: "dense BF16-MFMA"}[sc.noise.xtalk_kind]
+                                  + " crosstalk" if sc.noise.enabled else "clean"),
+                   "envs": E, "taxels": T, "links": L, "steps_per_rollout": S,
+                   "envs_per_block": eb, "threads_per_block": threads},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "tg_readout_kernel", "algorithmic_bytes_per_launch": nbytes,
+                     "bytes_per_readout": nbytes / readouts, "kernel_ms_mean": ms,
+                     "kernel_ms_min": float(np.min(kernel_ms))},
+        "input_gen_s": gen_s,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(sc, inp)
+    print(json.dumps(rec), flush=True)
+    ro.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,283 @@
+"""Thin ctypes binding of the tg_readout C ABI (include/tg_readout.h).
+
+Argument marshalling only: every step of the readout runs in the HIP library.  PyTorch
+provides device memory and the current stream.  There is no fallback: if the compiled
+library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtg_readout.so")
+ABI_VERSION = 1
+
+TG_OUT_BITS, TG_OUT_DEPTH, TG_OUT_PROX, TG_OUT_FT = 1, 2, 4, 8
+TG_OUT_NOISY, TG_OUT_NORMAL, TG_OUT_SURFDIST, TG_OUT_LINK_SUMS = 16, 32, 64, 128
+OUT_ALL = 255
+
+
+class TgError(RuntimeError):
+    pass
+
+
+class TgSdfGrid(C.Structure):
+    _fields_ = [("n", C.c_int32), ("origin", C.c_float * 3), ("spacing", C.c_float), ("values", C.c_void_p)]
+
+
+class TgNoiseDesc(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("drift_sigma", C.c_float), ("white_sigma", C.c_float), ("bias", C.c_float),
+                ("quant_step", C.c_float), ("hyst_mode", C.c_int32), ("tau_load_steps", C.c_float),
+                ("tau_unload_steps", C.c_float), ("maxwell_beta", C.c_float), ("maxwell_tau_s", C.c_float),
+                ("dt_s", C.c_float), ("p_dead", C.c_float), ("stuck_lo", C.c_float), ("stuck_hi", C.c_float),
+                ("radius_rho", C.c_float), ("gain_lo", C.c_float), ("gain_hi", C.c_float),
+                ("xtalk_kind", C.c_int32), ("xtalk_chi", C.c_float), ("xtalk_sigma", C.c_float),
+                ("eta_off", C.c_float)]
+
+
+class TgReadoutConfig(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("num_envs", C.c_int32), ("num_links", C.c_int32),
+                ("num_taxels", C.c_int32), ("num_objects", C.c_int32), ("link_taxel_offset", C.c_void_p),
+                ("taxel_pos", C.c_void_p), ("taxel_normal", C.c_void_p), ("taxel_radius", C.c_void_p),
+                ("grids", C.c_void_p), ("k_n", C.c_float), ("c_n", C.c_float), ("alpha", C.c_float),
+                ("k_t", C.c_float), ("k_w", C.c_float), ("mu", C.c_float), ("prox_range", C.c_float),
+                ("eta_on", C.c_float), ("ft_spring_only", C.c_int32), ("noise_enabled", C.c_int32),
+                ("noise", TgNoiseDesc), ("output_mask", C.c_uint32)]
+
+
+class TgStepInputs(C.Structure):
+    _fields_ = [("link_state", C.c_void_p), ("obj_state", C.c_void_p), ("obj_id", C.c_void_p), ("step", C.c_int64)]
+
+
+class TgStepOutputs(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in ("contact_bits", "contact_bits_noisy", "depth", "prox", "surfdist", "ft",
+                                         "ft_noisy", "normal", "link_sums", "link_sums_noisy")]
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load the compiled HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TgError(f"HIP library not built: {LIB_PATH} (run python -m paper_2606_22332_amd.build)")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "tg_readout_create": ([P, P], C.c_int),
+        "tg_readout_step": ([P, P, P, P], C.c_int),
+        "tg_readout_rollout": ([P, P, P, C.c_int32, P], C.c_int),
+        "tg_readout_reset": ([P, P, C.c_int64, P], C.c_int),
+        "tg_readout_state_size": ([P, P], C.c_int),
+        "tg_readout_get_state": ([P, P, C.c_size_t, P], C.c_int),
+        "tg_readout_set_state": ([P, P, C.c_size_t, P], C.c_int),
+        "tg_readout_launch_shape": ([P, P, P], C.c_int),
+        "tg_readout_destroy": ([P], C.c_int),
+        "tg_readout_last_error": ([P], C.c_char_p),
+        "tg_status_string": ([C.c_int], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(lib, h, rc, what):
+    if rc != 0:
+        msg = lib.tg_readout_last_error(h).decode()
+        raise TgError(f"{what}: {lib.tg_status_string(rc).decode()} ({rc}): {msg}")
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def make_config(scene, output_mask: int = OUT_ALL, keep: Optional[list] = None) -> TgReadoutConfig:
+    """Marshal a synthetic scene (paper_2606_22332_amd.synth.Scene) into tg_readout_config.
+    Host arrays are kept alive in `keep` until create has copied them."""
+    keep = [] if keep is None else keep
+    lay = scene.layout
+    arrs = dict(off=np.ascontiguousarray(lay.link_offset, np.int32), pos=np.ascontiguousarray(lay.pos, np.float32),
+                nrm=np.ascontiguousarray(lay.normal, np.float32), rad=np.ascontiguousarray(lay.radius, np.float32))
+    keep.append(arrs)
+    grids = (TgSdfGrid * len(scene.grids))()
+    for i, g in enumerate(scene.grids):
+        v = np.ascontiguousarray(g.values, np.float32)
+        keep.append(v)
+        grids[i].n = g.n
+        grids[i].origin[:] = [float(x) for x in g.origin]
+        grids[i].spacing = float(g.spacing)
+        grids[i].values = v.ctypes.data
+    keep.append(grids)
+    f, nz = scene.force, scene.noise
+    cfg = TgReadoutConfig()
+    cfg.abi_version = ABI_VERSION
+    cfg.num_envs, cfg.num_links = scene.num_envs, lay.num_links
+    cfg.num_taxels, cfg.num_objects = lay.num_taxels, len(scene.grids)
+    cfg.link_taxel_offset, cfg.taxel_pos = arrs["off"].ctypes.data, arrs["pos"].ctypes.data
+    cfg.taxel_normal, cfg.taxel_radius = arrs["nrm"].ctypes.data, arrs["rad"].ctypes.data
+    cfg.grids = C.addressof(grids)
+    cfg.k_n, cfg.c_n, cfg.alpha, cfg.k_t, cfg.k_w, cfg.mu = f.k_n, f.c_n, f.alpha, f.k_t, f.k_w, f.mu
+    cfg.prox_range, cfg.eta_on, cfg.ft_spring_only = f.prox_range, f.eta_on, int(f.spring_only)
+    cfg.noise_enabled = int(nz.enabled)
+    n = cfg.noise
+    n.seed, n.drift_sigma, n.white_sigma, n.bias, n.quant_step = nz.seed, nz.drift_sigma, nz.white_sigma, nz.bias, nz.quant_step
+    n.hyst_mode, n.tau_load_steps, n.tau_unload_steps = nz.hyst_mode, nz.tau_load_steps, nz.tau_unload_steps
+    n.maxwell_beta, n.maxwell_tau_s, n.dt_s = nz.maxwell_beta, nz.maxwell_tau_s, nz.dt_s
+    n.p_dead, n.stuck_lo, n.stuck_hi = nz.p_dead, nz.stuck_lo, nz.stuck_hi
+    n.radius_rho, n.gain_lo, n.gain_hi = nz.radius_rho, nz.gain_lo, nz.gain_hi
+    n.xtalk_kind, n.xtalk_chi, n.xtalk_sigma, n.eta_off = nz.xtalk_kind, nz.xtalk_chi, nz.xtalk_sigma, nz.eta_off
+    if not nz.enabled:
+        output_mask &= ~TG_OUT_NOISY
+    cfg.output_mask = output_mask
+    return cfg
+
+
+@dataclass
+class DeviceInputs:
+    link_state: "object"          # torch float32 [S,13,E*L] on cuda
+    obj_id: "object"              # torch int32 [S,E]
+    obj_state: "object" = None    # torch float32 [S,13,E] or None
+    step0: int = 0
+
+
+def to_device(inp, device="cuda") -> DeviceInputs:
+    import torch
+    ls = torch.from_numpy(np.ascontiguousarray(inp.link_state, np.float32)).to(device)
+    oid = torch.from_numpy(np.ascontiguousarray(inp.obj_id, np.int32)).to(device)
+    ost = None
+    if inp.obj_state is not None:
+        ost = torch.from_numpy(np.ascontiguousarray(inp.obj_state, np.float32)).to(device)
+    return DeviceInputs(ls, oid, ost, int(inp.step0))
+
+
+class Readout:
+    """A tg_readout handle plus torch-allocated output buffers for up to `max_steps` steps."""
+
+    def __init__(self, scene, output_mask: int = OUT_ALL, device: str = "cuda"):
+        import torch
+        self.lib = load()
+        self.scene = scene
+        keep: list = []
+        cfg = make_config(scene, output_mask, keep)
+        self.mask = cfg.output_mask
+        h = C.c_void_p()
+        rc = self.lib.tg_readout_create(C.byref(cfg), C.byref(h))
+        _check(self.lib, None, rc, "tg_readout_create")
+        self.h = h
+        self.device = device
+        self.E, self.L, self.T = scene.num_envs, scene.layout.num_links, scene.layout.num_taxels
+        self.W = (self.T + 63) // 64
+        self._torch = torch
+        self.out: Dict[str, "object"] = {}
+        self._out_steps = 0
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.tg_readout_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def launch_shape(self):
+        eb, th = C.c_int32(), C.c_int32()
+        _check(self.lib, self.h, self.lib.tg_readout_launch_shape(self.h, C.byref(eb), C.byref(th)), "launch_shape")
+        return eb.value, th.value
+
+    def alloc_outputs(self, steps: int):
+        torch = self._torch
+        E, T, L, W, m = self.E, self.T, self.L, self.W, self.mask
+        dev = self.device
+        f32 = dict(dtype=torch.float32, device=dev)
+        o = {}
+        if m & TG_OUT_BITS:
+            o["bits"] = torch.zeros((steps, E, W), dtype=torch.int64, device=dev)
+        if m & TG_OUT_DEPTH:
+            o["depth"] = torch.zeros((steps, E, T), **f32)
+        if m & TG_OUT_PROX:
+            o["prox"] = torch.zeros((steps, E, T), **f32)
+        if m & TG_OUT_SURFDIST:
+            o["surfdist"] = torch.zeros((steps, E, T), **f32)
+        if m & TG_OUT_FT:
+            o["ft"] = torch.zeros((steps, 6, E, T), **f32)
+        if m & TG_OUT_NOISY:
+            o["ft_noisy"] = torch.zeros((steps, 6, E, T), **f32)
+            o["bits_noisy"] = torch.zeros((steps, E, W), dtype=torch.int64, device=dev)
+        if m & TG_OUT_NORMAL:
+            o["normal"] = torch.zeros((steps, 3, E, T), **f32)
+        if m & TG_OUT_LINK_SUMS:
+            o["link_sums"] = torch.zeros((steps, 11, E, L), **f32)
+            if m & TG_OUT_NOISY:
+                o["link_sums_noisy"] = torch.zeros((steps, 11, E, L), **f32)
+        self.out = o
+        self._out_steps = steps
+        return o
+
+    def _outputs_struct(self, out, s0: int) -> TgStepOutputs:
+        def ptr(k):
+            t = out.get(k)
+            return None if t is None else t[s0].data_ptr()
+        return TgStepOutputs(ptr("bits"), ptr("bits_noisy"), ptr("depth"), ptr("prox"), ptr("surfdist"), ptr("ft"),
+                             ptr("ft_noisy"), ptr("normal"), ptr("link_sums"), ptr("link_sums_noisy"))
+
+    def rollout(self, dinp: DeviceInputs, n_steps: Optional[int] = None, s_in: int = 0, s_out: int = 0,
+                out=None, stream=None):
+        """Steps s_in .. s_in+n-1 of the device inputs into output slots s_out .., one launch."""
+        S = dinp.link_state.shape[0] if n_steps is None else n_steps
+        out = self.out if out is None else out
+        ist = TgStepInputs(dinp.link_state[s_in].data_ptr(),
+                           None if dinp.obj_state is None else dinp.obj_state[s_in].data_ptr(),
+                           dinp.obj_id[s_in].data_ptr(), dinp.step0 + s_in)
+        ost = self._outputs_struct(out, s_out)
+        rc = self.lib.tg_readout_rollout(self.h, C.byref(ist), C.byref(ost), int(S), _stream_ptr(stream))
+        _check(self.lib, self.h, rc, "tg_readout_rollout")
+
+    def step(self, dinp: DeviceInputs, s: int, s_out: Optional[int] = None, stream=None):
+        out = self.out
+        ist = TgStepInputs(dinp.link_state[s].data_ptr(),
+                           None if dinp.obj_state is None else dinp.obj_state[s].data_ptr(),
+                           dinp.obj_id[s].data_ptr(), dinp.step0 + s)
+        ost = self._outputs_struct(out, s if s_out is None else s_out)
+        rc = self.lib.tg_readout_step(self.h, C.byref(ist), C.byref(ost), _stream_ptr(stream))
+        _check(self.lib, self.h, rc, "tg_readout_step")
+
+    def reset(self, env_mask=None, step: int = 0, stream=None):
+        ptr = None if env_mask is None else env_mask.data_ptr()
+        rc = self.lib.tg_readout_reset(self.h, ptr, int(step), _stream_ptr(stream))
+        _check(self.lib, self.h, rc, "tg_readout_reset")
+
+    def state_size(self) -> int:
+        n = C.c_size_t()
+        _check(self.lib, self.h, self.lib.tg_readout_state_size(self.h, C.byref(n)), "state_size")
+        return n.value
+
+    def get_state(self, buf, stream=None):
+        _check(self.lib, self.h, self.lib.tg_readout_get_state(self.h, buf.data_ptr(), buf.numel() * buf.element_size(),
+                                                               _stream_ptr(stream)), "get_state")
+
+    def set_state(self, buf, stream=None):
+        _check(self.lib, self.h, self.lib.tg_readout_set_state(self.h, buf.data_ptr(), buf.numel() * buf.element_size(),
+                                                               _stream_ptr(stream)), "set_state")
+
+
+def unpack_bits(words: np.ndarray, T: int) -> np.ndarray:
+    """[..., W] int64/uint64 words -> [..., T] uint8 (bit j%64 of word j/64)."""
+    w = np.ascontiguousarray(words).view(np.uint64)
+    b = np.unpackbits(w.view(np.uint8).reshape(w.shape + (8,)), axis=-1, bitorder="little")
+    return b.reshape(w.shape[:-1] + (w.shape[-1] * 64,))[..., :T]

@@ -1,0 +1,263 @@
+// The fused tactile readout kernel: probe transform -> grid SDF -> depth, contact bit,
+// normal -> relative velocity -> force/torque and proximity -> noise model -> per-link
+// observations, for a block of whole environments, looping over steps inside the kernel.
+//
+// Thread mapping: one thread per (env, taxel) readout.  A block owns `eb` consecutive envs
+// (eb * T <= 1024 threads) for every step of the launch, so its noise state (drift, lag or
+// Maxwell, Schmitt bit, dead flag, stuck value, gain) lives in registers for the whole
+// rollout and touches HBM once at the start and once at the end.
+//
+// Per step the block stages the link poses of its envs in LDS (one thread per (env, link)
+// builds the rotation matrix), every thread gathers the 8 grid corners of its probe from
+// the object's grid (L2 / Infinity Cache resident), forms the outputs and writes them with
+// unit-stride stores.  Contact bits are assembled in LDS words and stored as 64-bit words.
+// Crosstalk (banded) reads in-link neighbours from LDS; dense crosstalk runs on MFMA.
+// Per-link sums are reduced from LDS by groups of 8 lanes.
+#pragma once
+#include "readout_device.h"
+
+namespace tg {
+
+struct KParams {
+  // sizes
+  int32_t E, L, T, n_obj, W;     // W = 64-bit words per env of a bit mask
+  int32_t eb;                    // envs per block
+  int32_t n_steps;
+  int64_t step0;
+  // constants
+  const float4* taxA;            // [T] x_j (xyz), R_j
+  const float4* taxB;            // [T] n_j (xyz), link index (int bits)
+  const int32_t* link_off;       // [L+1]
+  const GridDesc* grids;
+  const float* grid_vals;
+  float k_n, c_n, alpha, nk_t, k_w, mu, Rp, rpinv, eta_on, eta_off;
+  int32_t alpha_is_one, spring_only;
+  // noise
+  uint32_t key0, key1;
+  float drift_sigma, white_sigma, bias, quant, qinv;
+  float kload, kunload, decay, beta;
+  float two_rho, neg_rho;
+  float chi;
+  int32_t has_gain, has_stuck, has_radius;
+  // noise state (library-owned)
+  float* drift;                  // [6][E][T]
+  float* hyst;                   // [6][E][T]
+  float* hyst_prev;              // [6][E][T]
+  uint8_t* schmitt;              // [E][T]
+  uint8_t* dead;                 // [E][T]
+  float* stuck;                  // [E][T]
+  float* gain;                   // [E][T]
+  // inputs (per step strides implied by sizes)
+  const float* link_state;       // [S][13][E*L]
+  const float* obj_state;        // [S][13][E] or null
+  const int32_t* obj_id;         // [S][E]
+  // outputs (null = not requested)
+  unsigned long long* bits;      // [S][E][W]
+  unsigned long long* bits_noisy;
+  float* depth;                  // [S][E][T]
+  float* prox;
+  float* surfdist;
+  float* ft;                     // [S][6][E][T]
+  float* ft_noisy;
+  float* normal;                 // [S][3][E][T]
+  float* link_sums;              // [S][11][E][L]
+  float* link_sums_noisy;
+  // dense crosstalk (kind 2)
+  const uint2* xt_afrag;         // A fragments, 4 bf16 per lane, 64 lanes per 16x16 tile
+  const int4* xt_items;          // per MFMA row-tile item: (link, mtile, first A tile, n k-tiles)
+  int32_t xt_n_items;
+  int32_t tpad;                  // padded taxels per env in the MFMA staging layout
+  const int32_t* xt_poff;        // [L] padded offset of each link
+};
+
+struct TaxelOut {
+  float depth, phi, prox, surf;
+  float f[3], tau[3], mb[3];
+  bool active, far;
+};
+
+// Clean readout of one probe; the operation sequence is fixed (see readout_device.h).
+__device__ __forceinline__ void readout_probe(const KParams& p, const Pose& Lp, const Pose* Op, int oid, float4 ta,
+                                              float4 tb, TaxelOut& o) {
+  o.depth = 0.f; o.phi = 0.f; o.prox = 0.f; o.surf = 3.402823466e+38f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { o.f[i] = 0.f; o.tau[i] = 0.f; o.mb[i] = 0.f; }
+  o.active = false; o.far = false;
+  const float Rj = ta.w;
+  if (oid < 0 || oid >= p.n_obj || !(Rj > 0.f)) return;
+  o.active = true;
+  const float xj[3] = {ta.x, ta.y, ta.z};
+  float q[3], qo[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    q[i] = fmaf(Lp.R[3 * i + 2], xj[2], fmaf(Lp.R[3 * i + 1], xj[1], fmaf(Lp.R[3 * i], xj[0], Lp.p[i])));
+  if (Op) {
+    mat_T_vec(Op->R, q[0] - Op->p[0], q[1] - Op->p[1], q[2] - Op->p[2], qo);
+  } else {
+    qo[0] = q[0]; qo[1] = q[1]; qo[2] = q[2];
+  }
+  const GridDesc g = p.grids[oid];
+  float u[3];
+  bool far = false;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    u[i] = (qo[i] - g.origin[i]) * g.hinv;
+    far |= !(u[i] >= 0.f && u[i] <= g.nm1);
+  }
+  float uc[3], t[3];
+  int ii[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    uc[i] = far ? (u[i] > 0.f ? (u[i] < g.nm1 ? u[i] : g.nm1) : 0.f) : u[i];
+    int k = (int)floorf(uc[i]);
+    k = k > g.n - 2 ? g.n - 2 : k;
+    ii[i] = k;
+    t[i] = uc[i] - (float)k;
+  }
+  const float* G = p.grid_vals + g.offset;
+  const int N = g.n;
+  const int64_t base = ((int64_t)ii[2] * N + ii[1]) * N + ii[0];
+  const int64_t sy = N, sz = (int64_t)N * N;
+  const float c000 = G[base], c100 = G[base + 1];
+  const float c010 = G[base + sy], c110 = G[base + sy + 1];
+  const float c001 = G[base + sz], c101 = G[base + sz + 1];
+  const float c011 = G[base + sz + sy], c111 = G[base + sz + sy + 1];
+  const float l00 = lerpf(t[0], c000, c100), l10 = lerpf(t[0], c010, c110);
+  const float l01 = lerpf(t[0], c001, c101), l11 = lerpf(t[0], c011, c111);
+  const float phi = lerpf(t[2], lerpf(t[1], l00, l10), lerpf(t[1], l01, l11));
+  if (far) {
+    const float du0 = u[0] - uc[0], du1 = u[1] - uc[1], du2 = u[2] - uc[2];
+    o.far = true;
+    o.surf = phi + sqrtf(fmaf(du2, du2, fmaf(du1, du1, du0 * du0))) * g.spacing;
+    return;
+  }
+  o.surf = phi;
+  o.phi = phi;
+  const float diff = Rj - phi;
+  const float d = diff > 0.f ? diff : 0.f;
+  o.depth = d;
+  {
+    float w = (p.Rp - phi) * p.rpinv;
+    w = w > 0.f ? (w < 1.f ? w : 1.f) : 0.f;
+    o.prox = (w * w) * (3.0f - 2.0f * w);
+  }
+  if (!(d > 0.f)) return;
+  // contact normal: analytic gradient of the same trilinear interpolant
+  const float gx = lerpf(t[2], lerpf(t[1], c100 - c000, c110 - c010), lerpf(t[1], c101 - c001, c111 - c011));
+  const float gy = lerpf(t[2], lerpf(t[0], c010 - c000, c110 - c100), lerpf(t[0], c011 - c001, c111 - c101));
+  const float gz = lerpf(t[1], lerpf(t[0], c001 - c000, c101 - c100), lerpf(t[0], c011 - c010, c111 - c110));
+  const float n2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
+  float m[3], mb[3];
+  if (n2 > 0.f) {
+    const float inv = 1.0f / sqrtf(n2);
+    const float mh0 = gx * inv, mh1 = gy * inv, mh2 = gz * inv;
+    if (Op) {
+      mat_vec(Op->R, mh0, mh1, mh2, m);
+    } else {
+      m[0] = mh0; m[1] = mh1; m[2] = mh2;
+    }
+    mat_T_vec(Lp.R, m[0], m[1], m[2], mb);
+  } else {
+    float a[3];
+    mat_vec(Lp.R, tb.x, tb.y, tb.z, a);
+    m[0] = -a[0]; m[1] = -a[1]; m[2] = -a[2];
+    mb[0] = -tb.x; mb[1] = -tb.y; mb[2] = -tb.z;
+  }
+  // relative point velocity in the link frame
+  const float rL[3] = {q[0] - Lp.p[0], q[1] - Lp.p[1], q[2] - Lp.p[2]};
+  float cw[3], dv[3], dw[3], vr[3];
+  cross3(Lp.w, rL, cw);
+  const float vLq[3] = {Lp.v[0] + cw[0], Lp.v[1] + cw[1], Lp.v[2] + cw[2]};
+  if (Op) {
+    const float rO[3] = {q[0] - Op->p[0], q[1] - Op->p[1], q[2] - Op->p[2]};
+    float cwo[3];
+    cross3(Op->w, rO, cwo);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      dv[i] = (Op->v[i] + cwo[i]) - vLq[i];
+      dw[i] = Op->w[i] - Lp.w[i];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      dv[i] = -vLq[i];
+      dw[i] = -Lp.w[i];
+    }
+  }
+  mat_T_vec(Lp.R, dv[0], dv[1], dv[2], vr);
+  const float s = p.alpha_is_one ? d : powf(d, p.alpha);
+  float f[3], tau[3];
+  if (p.spring_only) {
+    const float Fn = p.k_n * s;
+    f[0] = Fn * mb[0]; f[1] = Fn * mb[1]; f[2] = Fn * mb[2];
+    cross3(xj, f, tau);
+  } else {
+    const float vn = fmaf(vr[2], mb[2], fmaf(vr[1], mb[1], vr[0] * mb[0]));
+    float ft[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) ft[i] = p.nk_t * fmaf(-vn, mb[i], vr[i]);
+    const float ks = p.k_n * s, cs = p.c_n * s;
+    float Fn = fmaf(cs, vn, ks);
+    Fn = Fn > 0.f ? Fn : 0.f;
+    const float ftn2 = fmaf(ft[2], ft[2], fmaf(ft[1], ft[1], ft[0] * ft[0]));
+    const float lim = p.mu * Fn;
+    if (ftn2 > lim * lim) {
+      const float sc = lim / sqrtf(ftn2);
+      ft[0] = ft[0] * sc; ft[1] = ft[1] * sc; ft[2] = ft[2] * sc;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) f[i] = fmaf(Fn, mb[i], ft[i]);
+    const float tw = fmaf(dw[2], m[2], fmaf(dw[1], m[1], dw[0] * m[0]));
+    const float kt = p.k_w * tw;
+    float cx[3];
+    cross3(xj, f, cx);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tau[i] = fmaf(-kt, mb[i], cx[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { o.f[i] = f[i]; o.tau[i] = tau[i]; o.mb[i] = mb[i]; }
+}
+
+// Sum of `n` values v[k*stride] split over the 8 lanes of a group (lane sub = 0..7), reduced
+// with cross-lane shuffles; the result is valid in every lane of the group.
+__device__ __forceinline__ float group8_sum(const float* v, int n, int sub) {
+  float acc = 0.f;
+  for (int k = sub; k < n; k += 8) acc += v[k];
+  acc += __shfl_xor(acc, 4, 8);
+  acc += __shfl_xor(acc, 2, 8);
+  acc += __shfl_xor(acc, 1, 8);
+  return acc;
+}
+
+// Per-link sums of the 10 value channels in LDS `sv` ([10][nr]) to out [11][E][L] for the
+// block's envs: f(3) tau(3) count, agg_bool (count > 2), 1e4 * (sum d n_z, d n_y, d n_x).
+__device__ __forceinline__ void link_sums_from_lds(const KParams& p, const float* sv, int nr, int e0, float* out) {
+  const int items = p.eb * p.L * 10;
+  const int groups = blockDim.x >> 3;
+  const int sub = threadIdx.x & 7;
+  const int64_t EL = (int64_t)p.E * p.L;
+  for (int it0 = 0; it0 < items; it0 += groups) {
+    const int it = it0 + (threadIdx.x >> 3);
+    const bool ok = it < items;
+    const int ch = ok ? it % 10 : 0;
+    const int rest = ok ? it / 10 : 0;
+    const int l = rest % p.L, el = rest / p.L;
+    const int a = p.link_off[l], n = ok ? p.link_off[l + 1] - a : 0;
+    const int e = e0 + el;
+    const bool valid = ok && e < p.E;
+    const float sum = group8_sum(sv + (int64_t)ch * nr + el * p.T + a, valid ? n : 0, sub);
+    if (valid && sub == 0) {
+      const int64_t col = (int64_t)e * p.L + l;
+      if (ch < 6) {
+        out[ch * EL + col] = sum;
+      } else if (ch == 6) {
+        out[6 * EL + col] = sum;
+        out[7 * EL + col] = sum > 2.5f ? 1.f : 0.f;
+      } else {
+        out[(ch + 1) * EL + col] = 1.0e4f * sum;
+      }
+    }
+  }
+}
+
+}  // namespace tg
