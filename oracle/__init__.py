@@ -6,4 +6,5 @@ binding) never does.  The oracle shares no code with the product: it has its
 own C source, its own structs and its own Python marshalling; the two meet only
 in the seeded scene generator, which holds no readout arithmetic.
 """
-from .oracle import (Oracle, build, run_readout, philox4x32_10, bf16_round, dense_xtalk, u01)  # noqa: F401
+from .oracle import (Oracle, build, run_readout, philox4x32_10, bf16_round, dense_xtalk, u01,  # noqa: F401
+                     nsdf_num_params, nsdf_forward, nsdf_loss_grad, nsdf_adam)

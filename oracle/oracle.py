@@ -207,3 +207,51 @@ def dense_xtalk(scene) -> list:
         out.append(buf[off:off + k * k].reshape(k, k).copy())
         off += k * k
     return out
+
+
+# ------------------------------------------------------------------------------------------------
+# neural SDF surrogate (nsdf.c)
+# ------------------------------------------------------------------------------------------------
+def _nsdf_lib():
+    lib = _load()
+    if not getattr(lib, "_nsdf_ready", False):
+        lib.or_nsdf_num_params.restype = C.c_int
+        lib.or_nsdf_forward.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        lib.or_nsdf_loss_grad.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.or_nsdf_loss_grad.restype = C.c_double
+        lib.or_nsdf_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_double,
+                                     C.c_double, C.c_double, C.c_double]
+        lib._nsdf_ready = True
+    return lib
+
+
+def nsdf_num_params() -> int:
+    return int(_nsdf_lib().or_nsdf_num_params())
+
+
+def nsdf_forward(P, x, grad=False, bf16=False):
+    lib = _nsdf_lib()
+    P = np.ascontiguousarray(P, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    out = np.zeros(x.shape[0])
+    gx = np.zeros_like(x) if grad else None
+    lib.or_nsdf_forward(P.ctypes.data, x.shape[0], x.ctypes.data, out.ctypes.data, _ptr(gx), int(bf16))
+    return (out, gx) if grad else out
+
+
+def nsdf_loss_grad(P, x, target):
+    lib = _nsdf_lib()
+    P = np.ascontiguousarray(P, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    t = np.ascontiguousarray(target, np.float64)
+    g = np.zeros_like(P)
+    loss = lib.or_nsdf_loss_grad(P.ctypes.data, x.shape[0], x.ctypes.data, t.ctypes.data, g.ctypes.data)
+    return loss, g
+
+
+def nsdf_adam(P, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    lib = _nsdf_lib()
+    for a in (P, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = np.ascontiguousarray(g, np.float64)
+    lib.or_nsdf_adam(P.ctypes.data, m.ctypes.data, v.ctypes.data, g.ctypes.data, P.size, int(t), lr, b1, b2, eps)

@@ -233,25 +233,26 @@ static void SFX(readout)(const or_problem* P, const SFX(pose) * L, const SFX(pos
   }
 }
 
-/* Gaussian deviates for (env, taxel, step) of one stream (purpose base 0 = drift, 3 = white):
- * three Philox calls per pair of steps give 12 uniforms -> 6 Box-Muller pairs -> 12 normals;
- * step t uses the six of half (t & 1). */
-static void SFX(gauss6)(uint64_t seed, uint32_t env, uint32_t taxel, int64_t t, uint32_t purpose0, REAL g[6]) {
+/* Six Gaussian deviates for (env, taxel, step t) of one stream (purpose base p0: 0 = drift,
+ * 2 = white noise).  Box-Muller on pairs of uniforms from Philox4x32-10:
+ *   call (env, taxel, t, p0)        -> (x0,x1) -> ch0, ch1;  (x2,x3) -> ch2, ch3
+ *   call (env, taxel, t >> 1, p0+1) -> even t: (y0,y1) -> ch4, ch5;  odd t: (y2,y3) -> ch4, ch5
+ * i.e. 1.5 generator calls per step; the paper fixes only the distributions. */
+static void SFX(gauss6)(uint64_t seed, uint32_t env, uint32_t taxel, int64_t t, uint32_t p0, REAL g[6]) {
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-  uint32_t x[12];
-  for (int c = 0; c < 3; ++c) {
-    uint32_t ctr[4] = {env, taxel, (uint32_t)(t >> 1), purpose0 + (uint32_t)c};
-    or_philox4x32_10(ctr, key, x + 4 * c);
-  }
-  double gg[12];
-  for (int i = 0; i < 6; ++i) {
-    double ua = or_u01(x[2 * i]), ub = or_u01(x[2 * i + 1]);
+  uint32_t x[4], y[4];
+  uint32_t c0[4] = {env, taxel, (uint32_t)t, p0};
+  uint32_t c1[4] = {env, taxel, (uint32_t)(t >> 1), p0 + 1u};
+  or_philox4x32_10(c0, key, x);
+  or_philox4x32_10(c1, key, y);
+  const int h = (int)(t & 1);
+  const uint32_t pr[3][2] = {{x[0], x[1]}, {x[2], x[3]}, {y[2 * h], y[2 * h + 1]}};
+  for (int i = 0; i < 3; ++i) {
+    double ua = or_u01(pr[i][0]), ub = or_u01(pr[i][1]);
     double r = sqrt(-2.0 * log(ua));
-    gg[2 * i] = r * cos(2.0 * M_PI * ub);
-    gg[2 * i + 1] = r * sin(2.0 * M_PI * ub);
+    g[2 * i] = (REAL)(r * cos(2.0 * M_PI * ub));
+    g[2 * i + 1] = (REAL)(r * sin(2.0 * M_PI * ub));
   }
-  int h = (int)(t & 1);
-  for (int c = 0; c < 6; ++c) g[c] = (REAL)gg[6 * h + c];
 }
 
 int SFX(or_reset)(const or_problem* P, or_state* st, const uint8_t* env_mask, int64_t reset_step) {
@@ -409,7 +410,7 @@ int SFX(or_run)(const or_problem* P, const or_inputs* in, or_outputs* out, or_st
           const int dead = st->dead ? st->dead[k] : 0;
           REAL gd[6] = {0, 0, 0, 0, 0, 0}, gw[6] = {0, 0, 0, 0, 0, 0};
           if (P->drift_sigma != 0) SFX(gauss6)(P->seed, ge, (uint32_t)j, t, 0u, gd);
-          if (P->white_sigma != 0) SFX(gauss6)(P->seed, ge, (uint32_t)j, t, 3u, gw);
+          if (P->white_sigma != 0) SFX(gauss6)(P->seed, ge, (uint32_t)j, t, 2u, gw);
           for (int c = 0; c < 6; ++c) {
             const int64_t sk = (int64_t)c * ET + k;
             REAL x = zt[c * T + j];

@@ -1,0 +1,459 @@
+// The fused rollout kernel, organised by (link, env chunk) work items.
+//
+// A block owns one link l for `envs` consecutive environments and runs every step of the
+// launch for them: lane r <-> (env el = r / n_l, taxel k = r % n_l), about 512 readouts per
+// block whatever the link size (16..128 taxels), so uneven links waste few lanes, and two blocks
+// share a CU so that one block's memory latency hides behind the other's arithmetic.  Because a
+// block only ever sees one link, everything that couples taxels stays inside the block:
+//   - dense crosstalk C_l Z_l runs on MFMA with the six channels of all the block's envs as
+//     the N columns (N = 6 * envs, 24..120); the BF16 A fragments of every link (206 KB for the
+//     largest hand) stay resident in each XCD's L2 and a wave loads its M tile once per step;
+//   - banded crosstalk reads in-link neighbours from LDS;
+//   - per-link sums (force/torque, contact count, agg_force) are reduced inside the block.
+// The noise state (drift, lag / Maxwell, Schmitt bit, dead flag, stuck value, gain) of each
+// readout lives in registers for the whole launch and touches HBM only at its ends.
+//
+// Per step: the scalars of the next step's link poses are prefetched (one or two per lane) and
+// parked in LDS before the step's last barrier; the loader lanes turn them into rotation
+// matrices at the start of the step.  Then compute the readout, store the clean outputs
+// (unit-stride runs of n_l floats per env), assemble contact bits in LDS windows and merge them
+// into the [E][ceil(T/64)] words (words shared with a neighbouring link are merged with atomic
+// and/or), then the noise chain and its outputs.
+//
+// The physical block id is remapped so that each of the 8 XCDs works through a contiguous
+// range of items (neighbouring envs share objects, hence grid data in that XCD's L2).
+#pragma once
+#include "readout_kernel.h"
+#include "xtalk_dense.h"
+
+namespace tg {
+
+__device__ __forceinline__ void load_pose13(const float* base, int64_t stride, int64_t col, float* v) {
+#pragma unroll
+  for (int c = 0; c < 13; ++c) v[c] = base[c * stride + col];
+}
+
+__device__ __forceinline__ Pose pose_from13(const float* v) {
+  Pose P;
+  quat_to_R(v[3], v[4], v[5], v[6], P.R);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    P.p[i] = v[i];
+    P.v[i] = v[7 + i];
+    P.w[i] = v[10 + i];
+  }
+  return P;
+}
+
+// Sum of S[ch][el*n + k], k < n, for (el, ch) items handled by groups of 8 lanes; writes the
+// 11 link observations (f, tau, count, agg_bool, agg_force) of one step to `out`.
+template <class KP>
+__device__ __forceinline__ void link_reduce(KP& p, const LinkInfo& li, const float* S, int nthr, int e0, int l,
+                                            float* out) {
+  const int n = li.n, envs = li.envs;
+  const int items = envs * 10;
+  const int groups = blockDim.x >> 3;
+  const int sub = threadIdx.x & 7;
+  const int64_t EL = (int64_t)p.E * p.L;
+  for (int it0 = 0; it0 < items; it0 += groups) {
+    const int it = it0 + (threadIdx.x >> 3);
+    const bool ok = it < items;
+    const int ch = ok ? it % 10 : 0, el = ok ? it / 10 : 0;
+    const int e = e0 + el;
+    const bool valid = ok && e < p.E;
+    const float* v = S + ch * nthr + el * n;
+    float acc = 0.f;
+    if (valid)
+      for (int k = sub; k < n; k += 8) acc += v[k];
+    acc += __shfl_xor(acc, 4, 8);
+    acc += __shfl_xor(acc, 2, 8);
+    acc += __shfl_xor(acc, 1, 8);
+    if (valid && sub == 0) {
+      const int64_t col = (int64_t)e * p.L + l;
+      if (ch < 6) {
+        out[ch * EL + col] = acc;
+      } else if (ch == 6) {
+        out[6 * EL + col] = acc;
+        out[7 * EL + col] = acc > 2.5f ? 1.f : 0.f;
+      } else {
+        out[(ch + 1) * EL + col] = 1.0e4f * acc;
+      }
+    }
+  }
+}
+
+// Merge the LDS bit windows of this block's envs into the global [E][W] words of one step.
+template <class KP>
+__device__ __forceinline__ void store_bits(KP& p, const LinkInfo& li, const unsigned* win, int e0,
+                                           unsigned long long* out_step) {
+  const int nw = li.nwin;
+  const int wstart = li.off >> 6;
+  const int lo = li.off, hi = li.off + li.n;
+  for (int idx = threadIdx.x; idx < li.envs * nw; idx += blockDim.x) {
+    const int el = idx / nw, w = idx - el * nw;
+    const int e = e0 + el;
+    if (e >= p.E) continue;
+    const unsigned long long bits =
+        (unsigned long long)win[(el * nw + w) * 2] | ((unsigned long long)win[(el * nw + w) * 2 + 1] << 32);
+    const int gw = wstart + w;
+    const int a = max(lo, gw * 64), b = min(hi, gw * 64 + 64);
+    unsigned long long* dst = out_step + (int64_t)e * p.W + gw;
+    if (a == gw * 64 && b == gw * 64 + 64) {
+      *dst = bits;
+    } else {
+      const int sh = a - gw * 64, len = b - a;
+      const unsigned long long cov = (len >= 64 ? ~0ull : ((1ull << len) - 1ull)) << sh;
+      atomicAnd(dst, ~cov);
+      atomicOr(dst, bits & cov);
+    }
+  }
+}
+
+// FULL = 0 compiles out the knobs none of the shipped workloads use (white noise, bias,
+// quantisation, per-probe gain, probe-radius noise, normal / surface-distance outputs) so that
+// the common path fits in 128 VGPRs (4 waves per SIMD) without spilling.
+template <int NOISE, int XT, int HY, int OBJ, int FULL>
+__global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
+  // The handle's constants are read through a constant-memory pointer that is made opaque at the
+  // top of every step, so the compiler reloads them (scalar loads) within the step instead of
+  // keeping all of them live in SGPRs across the whole step loop.
+  typedef const __attribute__((address_space(4))) KParams* KcPtr;   // constant memory: scalar loads
+  KcPtr kc = (KcPtr)q.kc;
+#define TG_REFRESH() asm volatile("" : "+s"(kc))
+#define TG_REFRESH_PHASE() do {} while (0)
+#define p (*kc)
+  TG_REFRESH();
+  extern __shared__ __align__(16) unsigned char smem[];
+  // XCD-aware mapping of physical blocks to work items
+  const int per = p.n_items_pad >> 3;
+  const int item_id = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (item_id >= p.n_items) return;
+  const int2 item = p.items[item_id];
+  const int l = item.x, e0 = item.y;
+  const LinkInfo li = p.links[l];   // (copied: plain struct in registers)
+  const int n = li.n, envs = li.envs;
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;
+  LinkLds Ld;   // field by field: the source lives in the constant address space
+  Ld.pose = p.lds.pose; Ld.opose = p.lds.opose; Ld.oid = p.lds.oid; Ld.bits = p.lds.bits; Ld.sums = p.lds.sums;
+  Ld.xz = p.lds.xz; Ld.tax = p.lds.tax; Ld.gtab = p.lds.gtab; Ld.raw = p.lds.raw; Ld.bt = p.lds.bt; Ld.dt = p.lds.dt;
+  Ld.total = p.lds.total;
+  Pose* lpose = (Pose*)(smem + Ld.pose);
+  Pose* opose = (Pose*)(smem + Ld.opose);
+  int* oids = (int*)(smem + Ld.oid);
+  unsigned* bitw = (unsigned*)(smem + Ld.bits);
+  float* S = (float*)(smem + Ld.sums);
+  float* XZ = (float*)(smem + Ld.xz);
+  float4* TX = (float4*)(smem + Ld.tax);     // [n][2]: (x_j, R_j), (n_j, link)
+  GridDesc* GT = (GridDesc*)(smem + Ld.gtab);
+  float* RAW = (float*)(smem + Ld.raw);      // [2][14][envs] prefetched step inputs
+  const int winw = envs * li.nwin * 2;       // u32 words of one bit-window set
+
+  const int el = tid / n;
+  const int k = tid - el * n;
+  const int e = e0 + el;
+  const bool act = tid < envs * n && e < p.E;
+  const int j = li.off + k;
+  const int64_t ET = (int64_t)p.E * p.T;
+  const int64_t EL = (int64_t)p.E * p.L;
+  const int64_t kk = (int64_t)e * p.T + j;
+
+  for (int i = tid; i < n; i += nthr) {
+    TX[2 * i] = p.taxA[li.off + i];
+    TX[2 * i + 1] = p.taxB[li.off + i];
+  }
+  if (p.gtab_lds)
+    for (int i = tid; i < p.n_obj; i += nthr) GT[i] = p.grids[i];
+  // Step inputs: scalar c (13 link-pose values, then the object id) of env el at step s is
+  // parked at RAW[(s&1)][c][el].  Lane i < 14*envs owns scalar (c = i / envs, el = i % envs)
+  // for every step: one pointer and one per-step stride, fixed for the launch.
+  // Offsets are packed in one int per lane: >= 0 into link_state (per step +13*E*L), < -1 the
+  // object id -(off+2) (per step +E), -1 none.
+  const int nraw = 14 * envs;
+  int pf_off = -1;
+  if (tid < nraw) {
+    const int c = tid / envs, el_ = tid - c * envs;
+    if (e0 + el_ < p.E) pf_off = c < 13 ? (int)(c * EL + (int64_t)(e0 + el_) * p.L + l) : -(e0 + el_) - 2;
+  }
+  auto prefetch = [&](int s_) -> float {
+    if (pf_off >= 0) return q.link_state[(int64_t)s_ * 13 * EL + pf_off];
+    return __int_as_float(q.obj_id[(int64_t)s_ * p.E + (-pf_off - 2)]);
+  };
+  if (pf_off != -1) RAW[tid] = prefetch(0);
+  float D[6] = {0, 0, 0, 0, 0, 0}, Y[6] = {0, 0, 0, 0, 0, 0}, XP[6] = {0, 0, 0, 0, 0, 0};
+  uint32_t yd2 = 0u, yd3 = 0u;               // carried-over pair of the drift stream
+  bool sch = false, dead = false;
+  float stuck = 0.f, gain = 1.f;
+  if (NOISE && act) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      if (p.drift_sigma != 0.f) D[c] = p.drift[c * ET + kk];
+      if (HY) Y[c] = p.hyst[c * ET + kk];
+      if (HY == 2) XP[c] = p.hyst_prev[c * ET + kk];
+    }
+    sch = p.schmitt[kk] != 0;
+    dead = p.dead[kk] != 0;
+    if (p.has_stuck) stuck = p.stuck[kk];
+    if (FULL && p.has_gain) gain = p.gain[kk];
+  }
+  if (XT == 2) {   // zero the B staging once: padding rows and columns stay zero
+    uint32_t* bt = (uint32_t*)(smem + Ld.bt);
+    for (int i = tid; i < (li.nt * 16 * li.kp) / 2; i += nthr) bt[i] = 0u;
+  }
+  const bool loader = tid < envs && e0 + tid < p.E;
+  __syncthreads();   // LDS constants and the first step's inputs
+
+  for (int s = 0; s < q.n_steps; ++s) {
+    TG_REFRESH();
+    const int64_t t = q.step0 + s;
+    const int par = s & 1;
+    Pose* lp = lpose + par * envs;
+    Pose* op = opose + par * envs;
+    int* oi = oids + par * envs;
+    unsigned* bw = bitw + par * 2 * winw;
+    unsigned* bwn = bw + winw;
+    const float* rw = RAW + par * nraw;
+    if (loader) {
+      float pv[13];
+#pragma unroll
+      for (int c = 0; c < 13; ++c) pv[c] = rw[c * envs + tid];
+      lp[tid] = pose_from13(pv);
+      oi[tid] = __float_as_int(rw[13 * envs + tid]);
+      if (OBJ) {
+        load_pose13(q.obj_state + (int64_t)s * 13 * p.E, p.E, e0 + tid, pv);
+        op[tid] = pose_from13(pv);
+      }
+    }
+    for (int i = tid; i < 2 * winw; i += nthr) bw[i] = 0u;
+    __syncthreads();   // B1: poses, ids, zeroed bit windows
+    TG_REFRESH_PHASE();
+    // prefetch this lane's scalar of the next step's inputs; parked in LDS before the last barrier
+    const bool pre = s + 1 < q.n_steps;
+    float rv = 0.f;
+    if (pre && pf_off != -1) rv = prefetch(s + 1);
+
+    const float4 ta = act ? TX[2 * k] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float4 tb = act ? TX[2 * k + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    TaxelOut o;
+    if (act) {
+      readout_probe(p, GT, lp[el], OBJ ? &op[el] : nullptr, oi[el], ta, tb, o);
+    } else {
+      o.depth = 0.f; o.phi = 0.f; o.prox = 0.f; o.surf = 0.f; o.active = false; o.far = false;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) { o.f[i] = 0.f; o.tau[i] = 0.f; o.mb[i] = 0.f; }
+    }
+    const bool bit = o.depth > p.eta_on;
+    const int wbit = (li.off & 63) + k;   // bit position inside this env's window
+    if (act) {
+      const int64_t ok = (int64_t)s * ET + kk;
+      if (q.depth) q.depth[ok] = o.depth;
+      if (q.prox) q.prox[ok] = o.prox;
+      if (FULL && q.surfdist) q.surfdist[ok] = o.surf;
+      if (q.ft) {
+        float* f = q.ft + (int64_t)s * 6 * ET + kk;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { f[c * ET] = o.f[c]; f[(c + 3) * ET] = o.tau[c]; }
+      }
+      if (FULL && q.normal) {
+        float* nm = q.normal + (int64_t)s * 3 * ET + kk;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nm[c * ET] = o.mb[c];
+      }
+      if (bit) atomicOr(&bw[el * li.nwin * 2 + (wbit >> 5)], 1u << (wbit & 31));
+    }
+    const bool sums = q.link_sums != nullptr;
+    if (sums) {
+      S[0 * nthr + tid] = o.f[0]; S[1 * nthr + tid] = o.f[1]; S[2 * nthr + tid] = o.f[2];
+      S[3 * nthr + tid] = o.tau[0]; S[4 * nthr + tid] = o.tau[1]; S[5 * nthr + tid] = o.tau[2];
+      S[6 * nthr + tid] = bit ? 1.f : 0.f;
+      S[7 * nthr + tid] = o.depth * tb.z;
+      S[8 * nthr + tid] = o.depth * tb.y;
+      S[9 * nthr + tid] = o.depth * tb.x;
+    }
+    float z[6] = {gain * o.f[0], gain * o.f[1], gain * o.f[2], gain * o.tau[0], gain * o.tau[1], gain * o.tau[2]};
+    if (NOISE && XT == 1) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) XZ[c * nthr + tid] = z[c];
+    }
+    if (NOISE && XT == 2 && act) {
+      uint16_t* bt = (uint16_t*)(smem + Ld.bt);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) bt[(6 * el + c) * li.kp + k] = (uint16_t)bf16_bits(z[c]);
+    }
+    if (!NOISE && pre && pf_off != -1) RAW[(par ^ 1) * nraw + tid] = rv;   // the other parity is free
+    __syncthreads();   // B2: clean bits, sums, crosstalk operands
+    TG_REFRESH_PHASE();
+    if (q.bits) store_bits(p, li, bw, e0, q.bits + (int64_t)s * p.E * p.W);
+    if (sums) link_reduce(p, li, S, nthr, e0, l, q.link_sums + (int64_t)s * 11 * EL);
+
+    if (NOISE) {
+      if (XT == 2) {
+        // C_l Z on MFMA.  Wave w takes M tile w % MT and every G-th N tile (G = waves per M tile),
+        // so it fetches its A fragments (one per K tile, L2-resident) once per step.
+        const uint16_t* bt = (const uint16_t*)(smem + Ld.bt);
+        float* dt = (float*)(smem + Ld.dt);
+        const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
+        const int ncols = 6 * envs;
+        const int G = nwaves >= li.mt ? nwaves / li.mt : 1;
+        for (int mt = wave % li.mt; mt < li.mt && wave < G * li.mt; mt += nwaves) {
+          const uint2* arow = p.xt_afrag + ((int64_t)li.afrag_off + (int64_t)mt * li.kt) * 64 + lane;
+          uint2 afr[8];
+#pragma unroll
+          for (int kt = 0; kt < 8; ++kt) afr[kt] = kt < li.kt ? arow[kt * 64] : make_uint2(0u, 0u);
+          for (int nt = (nwaves >= li.mt ? wave / li.mt : 0); nt < li.nt; nt += G) {
+            const int col = nt * 16 + (lane & 15);
+            const uint16_t* bcol = bt + col * li.kp + 4 * (lane >> 4);
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kt = 0; kt < 8; ++kt) {
+              if (kt < li.kt) {
+                const uint2 b = *(const uint2*)(bcol + 16 * kt);
+                bf16x4 av, bv;
+                __builtin_memcpy(&av, &afr[kt], 8);
+                __builtin_memcpy(&bv, &b, 8);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+              }
+            }
+            for (int kt = 8; kt < li.kt; ++kt) {   // links of more than 128 taxels
+              const uint2 a = arow[kt * 64];
+              const uint2 b = *(const uint2*)(bcol + 16 * kt);
+              bf16x4 av, bv;
+              __builtin_memcpy(&av, &a, 8);
+              __builtin_memcpy(&bv, &b, 8);
+              acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+            }
+            if (col < ncols) {
+              const int m0 = 16 * mt + 4 * (lane >> 4);
+#pragma unroll
+              for (int r = 0; r < 4; ++r) dt[col * li.kpd + m0 + r] = acc[r];
+            }
+          }
+        }
+      }
+      __syncthreads();   // B3: crosstalk results; the clean reduction is done with S
+      TG_REFRESH_PHASE();
+      float zt[6];
+      if (XT == 1) {
+        const float chi = p.chi;
+        const bool hasl = k > 0, hasr = k < n - 1;
+        const float cjj = 1.0f - chi * (float)((int)hasl + (int)hasr);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          float acc = cjj * z[c];
+          if (act && hasl) acc = fmaf(chi, XZ[c * nthr + tid - 1], acc);
+          if (act && hasr) acc = fmaf(chi, XZ[c * nthr + tid + 1], acc);
+          zt[c] = acc;
+        }
+      } else if (XT == 2) {
+        const float* dt = (const float*)(smem + Ld.dt);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) zt[c] = act ? dt[(6 * el + c) * li.kpd + k] : 0.f;
+      } else {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) zt[c] = z[c];
+      }
+      // Gaussian streams: one Philox call per step for channels 0-3, one per pair of steps for
+      // channels 4-5 (its second pair is carried over to the odd step)
+      const bool odd = (t & 1) != 0;
+      float gd[6], gw[6];
+      if (p.drift_sigma != 0.f) {
+        gauss4(p.key0, p.key1, (uint32_t)e, (uint32_t)j, (uint32_t)t, 0u, gd);
+        uint32_t ya, yb;
+        if (!odd || s == 0) {
+          uint32_t y0, y1, y2, y3;
+          pair_call(p.key0, p.key1, (uint32_t)e, (uint32_t)j, (uint32_t)(t >> 1), 0u, y0, y1, y2, y3);
+          ya = odd ? y2 : y0;
+          yb = odd ? y3 : y1;
+          yd2 = y2;
+          yd3 = y3;
+        } else {
+          ya = yd2;
+          yb = yd3;
+        }
+        box_muller(ya, yb, gd[4], gd[5]);
+      }
+      if (FULL && p.white_sigma != 0.f) {   // (both calls made every step)
+        gauss4(p.key0, p.key1, (uint32_t)e, (uint32_t)j, (uint32_t)t, 2u, gw);
+        uint32_t y0, y1, y2, y3;
+        pair_call(p.key0, p.key1, (uint32_t)e, (uint32_t)j, (uint32_t)(t >> 1), 2u, y0, y1, y2, y3);
+        box_muller(odd ? y2 : y0, odd ? y3 : y1, gw[4], gw[5]);
+      }
+      float fo[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const float x = zt[c];
+        float h = x;
+        if (HY == 1) {
+          const float kap = fabsf(x) > fabsf(Y[c]) ? p.kload : p.kunload;
+          Y[c] = fmaf(kap, x - Y[c], Y[c]);
+          h = Y[c];
+        } else if (HY == 2) {
+          Y[c] = fmaf(p.decay, Y[c], x - XP[c]);
+          XP[c] = x;
+          h = fmaf(p.beta, Y[c], x);
+        }
+        float v = h;
+        if (FULL && p.bias != 0.f) v = v + p.bias;
+        if (FULL && p.white_sigma != 0.f) v = fmaf(p.white_sigma, gw[c], v);
+        if (p.drift_sigma != 0.f) {
+          D[c] = fmaf(p.drift_sigma, gd[c], D[c]);
+          v = v + D[c];
+        }
+        if (FULL && p.quant > 0.f) v = p.quant * rintf(v * p.qinv);
+        if (dead) v = stuck;
+        fo[c] = v;
+      }
+      if (act && q.ft_noisy) {
+        float* f = q.ft_noisy + (int64_t)s * 6 * ET + kk;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) f[c * ET] = fo[c];
+      }
+      float dd = o.depth;
+      if (FULL && p.has_radius) {
+        dd = 0.f;
+        if (act && o.active && !o.far) {
+          uint32_t x0 = (uint32_t)e, x1 = (uint32_t)j, x2 = (uint32_t)t, x3 = 6u;
+          philox4x32_10(x0, x1, x2, x3, p.key0, p.key1);
+          float Rn = ta.w + fmaf(u01(x0), p.two_rho, p.neg_rho);
+          Rn = Rn > 0.f ? Rn : 0.f;
+          const float df = Rn - o.phi;
+          dd = df > 0.f ? df : 0.f;
+        }
+      }
+      bool nb = (dd > p.eta_on) || (sch && dd > p.eta_off);
+      if (dead) { nb = false; dd = 0.f; }
+      sch = nb;
+      if (act && nb) atomicOr(&bwn[el * li.nwin * 2 + (wbit >> 5)], 1u << (wbit & 31));
+      const bool sums_n = q.link_sums_noisy != nullptr;
+      if (sums_n) {
+        const float4 tn = act ? TX[2 * k + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
+        S[0 * nthr + tid] = fo[0]; S[1 * nthr + tid] = fo[1]; S[2 * nthr + tid] = fo[2];
+        S[3 * nthr + tid] = fo[3]; S[4 * nthr + tid] = fo[4]; S[5 * nthr + tid] = fo[5];
+        S[6 * nthr + tid] = nb ? 1.f : 0.f;
+        S[7 * nthr + tid] = dd * tn.z;
+        S[8 * nthr + tid] = dd * tn.y;
+        S[9 * nthr + tid] = dd * tn.x;
+      }
+      if (pre && pf_off != -1) RAW[(par ^ 1) * nraw + tid] = rv;   // park the next step's inputs
+      __syncthreads();   // B4: noisy bits and sums
+      TG_REFRESH_PHASE();
+      if (q.bits_noisy) store_bits(p, li, bwn, e0, q.bits_noisy + (int64_t)s * p.E * p.W);
+      if (sums_n) link_reduce(p, li, S, nthr, e0, l, q.link_sums_noisy + (int64_t)s * 11 * EL);
+    }
+  }
+  TG_REFRESH();
+  if (NOISE && act) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      if (p.drift_sigma != 0.f) p.drift[c * ET + kk] = D[c];
+      if (HY) p.hyst[c * ET + kk] = Y[c];
+      if (HY == 2) p.hyst_prev[c * ET + kk] = XP[c];
+    }
+    p.schmitt[kk] = sch ? 1 : 0;
+  }
+}
+
+#undef p
+#undef TG_REFRESH
+#undef TG_REFRESH_PHASE
+}  // namespace tg

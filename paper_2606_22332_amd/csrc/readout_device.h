@@ -68,8 +68,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
                                               uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     const uint32_t n0 = hi1 ^ c1 ^ k0;
     const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -92,17 +94,21 @@ __device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, float& g0, 
   g1 = r * __builtin_amdgcn_sinf(ub);
 }
 
-// Twelve normals for (env, taxel, pair of steps t>>1): three Philox calls with purposes
-// base, base+1, base+2; step t uses the six of half (t & 1).
-__device__ __forceinline__ void gauss12(uint32_t k0, uint32_t k1, uint32_t env, uint32_t taxel, uint32_t pair,
-                                        uint32_t base, float* g) {
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    uint32_t x0 = env, x1 = taxel, x2 = pair, x3 = base + (uint32_t)c;
-    philox4x32_10(x0, x1, x2, x3, k0, k1);
-    box_muller(x0, x1, g[4 * c + 0], g[4 * c + 1]);
-    box_muller(x2, x3, g[4 * c + 2], g[4 * c + 3]);
-  }
+// Gaussian stream layout (purpose base p0: 0 = drift, 2 = white noise), per (env, taxel, t):
+//   Philox(env, taxel, t, p0)        -> Box-Muller (x0,x1) -> ch0, ch1; (x2,x3) -> ch2, ch3
+//   Philox(env, taxel, t >> 1, p0+1) -> even t: (y0,y1) -> ch4, ch5; odd t: (y2,y3) -> ch4, ch5
+// The second call serves two consecutive steps; its second pair can be carried over.
+__device__ __forceinline__ void gauss4(uint32_t k0, uint32_t k1, uint32_t env, uint32_t taxel, uint32_t t,
+                                       uint32_t p0, float* g) {
+  uint32_t x0 = env, x1 = taxel, x2 = t, x3 = p0;
+  philox4x32_10(x0, x1, x2, x3, k0, k1);
+  box_muller(x0, x1, g[0], g[1]);
+  box_muller(x2, x3, g[2], g[3]);
+}
+__device__ __forceinline__ void pair_call(uint32_t k0, uint32_t k1, uint32_t env, uint32_t taxel, uint32_t tpair,
+                                          uint32_t p0, uint32_t& y0, uint32_t& y1, uint32_t& y2, uint32_t& y3) {
+  y0 = env; y1 = taxel; y2 = tpair; y3 = p0 + 1u;
+  philox4x32_10(y0, y1, y2, y3, k0, k1);
 }
 
 // BF16 (round to nearest even) of a finite FP32 value, as the 16-bit pattern.

@@ -18,12 +18,24 @@
 
 namespace tg {
 
+// One link of the hand as the kernel sees it.
+struct LinkInfo {
+  int32_t off, n;        // first taxel, taxel count
+  int32_t envs;          // envs per block for this link
+  int32_t nwin;          // 64-bit words spanned by [off, off+n)
+  int32_t mt, kt, nt;    // dense crosstalk: M tiles, K tiles (16 rows each), N tiles of 16 columns
+  int32_t kp, kpd;       // padded K stride (bf16 elements) of the B staging, of the result staging
+  int32_t afrag_off;     // first A tile of this link in the fragment buffer
+};
+
+// LDS carve-up (byte offsets), identical for every block of a launch.
+struct LinkLds {
+  int32_t pose, opose, oid, bits, sums, xz, tax, gtab, raw, bt, dt, total;
+};
+
 struct KParams {
   // sizes
   int32_t E, L, T, n_obj, W;     // W = 64-bit words per env of a bit mask
-  int32_t eb;                    // envs per block
-  int32_t n_steps;
-  int64_t step0;
   // constants
   const float4* taxA;            // [T] x_j (xyz), R_j
   const float4* taxB;            // [T] n_j (xyz), link index (int bits)
@@ -47,6 +59,22 @@ struct KParams {
   uint8_t* dead;                 // [E][T]
   float* stuck;                  // [E][T]
   float* gain;                   // [E][T]
+  // work items: one block per (link, env chunk)
+  const int2* items;             // (link, first env)
+  const LinkInfo* links;         // [L]
+  int32_t n_items, n_items_pad;  // pad = multiple of 8 (XCD-aware remapping)
+  int32_t gtab_lds;              // 1: grid descriptors staged in LDS
+  LinkLds lds;
+  // dense crosstalk (kind 2)
+  const uint2* xt_afrag;         // A fragments, 4 bf16 per lane, 64 lanes per 16x16 tile
+};
+
+// Per-launch arguments (kernel arguments); everything fixed for a handle lives in a KParams
+// copy in device memory that the kernel reads through an opaque pointer.
+struct KLaunch {
+  const KParams* kc;
+  int32_t n_steps;
+  int64_t step0;
   // inputs (per step strides implied by sizes)
   const float* link_state;       // [S][13][E*L]
   const float* obj_state;        // [S][13][E] or null
@@ -62,12 +90,6 @@ struct KParams {
   float* normal;                 // [S][3][E][T]
   float* link_sums;              // [S][11][E][L]
   float* link_sums_noisy;
-  // dense crosstalk (kind 2)
-  const uint2* xt_afrag;         // A fragments, 4 bf16 per lane, 64 lanes per 16x16 tile
-  const int4* xt_items;          // per MFMA row-tile item: (link, mtile, first A tile, n k-tiles)
-  int32_t xt_n_items;
-  int32_t tpad;                  // padded taxels per env in the MFMA staging layout
-  const int32_t* xt_poff;        // [L] padded offset of each link
 };
 
 struct TaxelOut {
@@ -77,8 +99,9 @@ struct TaxelOut {
 };
 
 // Clean readout of one probe; the operation sequence is fixed (see readout_device.h).
-__device__ __forceinline__ void readout_probe(const KParams& p, const Pose& Lp, const Pose* Op, int oid, float4 ta,
-                                              float4 tb, TaxelOut& o) {
+template <class KP>
+__device__ __forceinline__ void readout_probe(KP& p, const GridDesc* gtab, const Pose& Lp, const Pose* Op, int oid,
+                                              float4 ta, float4 tb, TaxelOut& o) {
   o.depth = 0.f; o.phi = 0.f; o.prox = 0.f; o.surf = 3.402823466e+38f;
 #pragma unroll
   for (int i = 0; i < 3; ++i) { o.f[i] = 0.f; o.tau[i] = 0.f; o.mb[i] = 0.f; }
@@ -96,7 +119,9 @@ __device__ __forceinline__ void readout_probe(const KParams& p, const Pose& Lp, 
   } else {
     qo[0] = q[0]; qo[1] = q[1]; qo[2] = q[2];
   }
-  const GridDesc g = p.grids[oid];
+  GridDesc g;
+  if (p.gtab_lds) g = gtab[oid];
+  else g = p.grids[oid];
   float u[3];
   bool far = false;
 #pragma unroll
@@ -116,8 +141,8 @@ __device__ __forceinline__ void readout_probe(const KParams& p, const Pose& Lp, 
   }
   const float* G = p.grid_vals + g.offset;
   const int N = g.n;
-  const int64_t base = ((int64_t)ii[2] * N + ii[1]) * N + ii[0];
-  const int64_t sy = N, sz = (int64_t)N * N;
+  const uint32_t base = ((uint32_t)ii[2] * (uint32_t)N + (uint32_t)ii[1]) * (uint32_t)N + (uint32_t)ii[0];
+  const uint32_t sy = (uint32_t)N, sz = (uint32_t)N * (uint32_t)N;
   const float c000 = G[base], c100 = G[base + 1];
   const float c010 = G[base + sy], c110 = G[base + sy + 1];
   const float c001 = G[base + sz], c101 = G[base + sz + 1];
@@ -216,48 +241,6 @@ __device__ __forceinline__ void readout_probe(const KParams& p, const Pose& Lp, 
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) { o.f[i] = f[i]; o.tau[i] = tau[i]; o.mb[i] = mb[i]; }
-}
-
-// Sum of `n` values v[k*stride] split over the 8 lanes of a group (lane sub = 0..7), reduced
-// with cross-lane shuffles; the result is valid in every lane of the group.
-__device__ __forceinline__ float group8_sum(const float* v, int n, int sub) {
-  float acc = 0.f;
-  for (int k = sub; k < n; k += 8) acc += v[k];
-  acc += __shfl_xor(acc, 4, 8);
-  acc += __shfl_xor(acc, 2, 8);
-  acc += __shfl_xor(acc, 1, 8);
-  return acc;
-}
-
-// Per-link sums of the 10 value channels in LDS `sv` ([10][nr]) to out [11][E][L] for the
-// block's envs: f(3) tau(3) count, agg_bool (count > 2), 1e4 * (sum d n_z, d n_y, d n_x).
-__device__ __forceinline__ void link_sums_from_lds(const KParams& p, const float* sv, int nr, int e0, float* out) {
-  const int items = p.eb * p.L * 10;
-  const int groups = blockDim.x >> 3;
-  const int sub = threadIdx.x & 7;
-  const int64_t EL = (int64_t)p.E * p.L;
-  for (int it0 = 0; it0 < items; it0 += groups) {
-    const int it = it0 + (threadIdx.x >> 3);
-    const bool ok = it < items;
-    const int ch = ok ? it % 10 : 0;
-    const int rest = ok ? it / 10 : 0;
-    const int l = rest % p.L, el = rest / p.L;
-    const int a = p.link_off[l], n = ok ? p.link_off[l + 1] - a : 0;
-    const int e = e0 + el;
-    const bool valid = ok && e < p.E;
-    const float sum = group8_sum(sv + (int64_t)ch * nr + el * p.T + a, valid ? n : 0, sub);
-    if (valid && sub == 0) {
-      const int64_t col = (int64_t)e * p.L + l;
-      if (ch < 6) {
-        out[ch * EL + col] = sum;
-      } else if (ch == 6) {
-        out[6 * EL + col] = sum;
-        out[7 * EL + col] = sum > 2.5f ? 1.f : 0.f;
-      } else {
-        out[(ch + 1) * EL + col] = 1.0e4f * sum;
-      }
-    }
-  }
 }
 
 }  // namespace tg

@@ -11,8 +11,7 @@
 #include <vector>
 
 #include "../../include/tg_readout.h"
-#include "readout_kernel.h"
-#include "xtalk_dense.h"
+#include "link_kernel.h"
 
 using namespace tg;
 
@@ -20,301 +19,9 @@ namespace {
 
 thread_local std::string g_create_error;
 
-constexpr int kSumCh = 10;   // value channels reduced per link
-
-// LDS layout of the readout kernel (bytes), shared by host sizing and device carving.
-struct LdsLayout {
-  size_t pose, opose, oid, bits, sums, xt, xtb, xtx, total;
-};
-
-__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
-
-__host__ __device__ inline LdsLayout lds_layout(int eb, int L, int T, int W, int noise, int xt, int tpad) {
-  LdsLayout o;
-  const size_t nr = (size_t)eb * T;
-  size_t off = 0;
-  o.pose = off; off = align16(off + 2 * (size_t)eb * L * sizeof(Pose));
-  o.opose = off; off = align16(off + 2 * (size_t)eb * sizeof(Pose));
-  o.oid = off; off = align16(off + 2 * (size_t)eb * sizeof(int));
-  o.bits = off; off = align16(off + 2 * 2 * (size_t)eb * 2 * W * sizeof(unsigned));
-  o.sums = off; off = align16(off + kSumCh * nr * sizeof(float));
-  o.xt = off; off = align16(off + (xt == 1 ? 6 * nr * sizeof(float) : 0));
-  o.xtb = off; off = align16(off + (xt == 2 ? 6 * (size_t)eb * tpad * sizeof(uint16_t) : 0));
-  o.xtx = off; off = align16(off + (xt == 2 ? 6 * (size_t)eb * tpad * sizeof(float) : 0));
-  o.total = off;
-  (void)noise;
-  return o;
-}
+inline int32_t align16i(int64_t x) { return (int32_t)((x + 15) & ~int64_t(15)); }
 
 }  // namespace
-
-// ------------------------------------------------------------------------------------------------
-// kernels
-// ------------------------------------------------------------------------------------------------
-template <int NOISE, int XT, int HY, int OBJ>
-__global__ void __launch_bounds__(1024) tg_readout_kernel(const KParams p) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int T = p.T, L = p.L, eb = p.eb, W = p.W;
-  const int nr = eb * T;
-  const int e0 = blockIdx.x * eb;
-  const int tid = threadIdx.x;
-  const LdsLayout lay = lds_layout(eb, L, T, W, NOISE, XT, p.tpad);
-  Pose* lpose = (Pose*)(smem + lay.pose);
-  Pose* opose = (Pose*)(smem + lay.opose);
-  int* oids = (int*)(smem + lay.oid);
-  unsigned* bitw = (unsigned*)(smem + lay.bits);   // [parity][clean,noisy][eb][2W]
-  float* sv = (float*)(smem + lay.sums);           // [10][nr]
-  float* xv = (float*)(smem + lay.xt);             // [6][nr]
-
-  const int el = tid / T;
-  const int e = e0 + el;
-  const bool act = tid < nr && e < p.E;
-  const int j = act ? tid - el * T : 0;
-  float4 ta = make_float4(0.f, 0.f, 0.f, 0.f), tb = ta;
-  int lk = 0, la = 0, lb = 0;
-  if (act) {
-    ta = p.taxA[j];
-    tb = p.taxB[j];
-    lk = __float_as_int(tb.w);
-    la = p.link_off[lk];
-    lb = p.link_off[lk + 1];
-  }
-  const int64_t ET = (int64_t)p.E * T;
-  const int64_t EL = (int64_t)p.E * L;
-  const int64_t kk = (int64_t)e * T + j;
-  const int words2 = 2 * W;
-
-  // ---- noise state: registers for the whole launch
-  float D[6] = {0, 0, 0, 0, 0, 0}, Y[6] = {0, 0, 0, 0, 0, 0}, XP[6] = {0, 0, 0, 0, 0, 0};
-  bool sch = false, dead = false;
-  float stuck = 0.f, gain = 1.f;
-  if (NOISE && act) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      if (p.drift_sigma != 0.f) D[c] = p.drift[c * ET + kk];
-      if (HY) Y[c] = p.hyst[c * ET + kk];
-      if (HY == 2) XP[c] = p.hyst_prev[c * ET + kk];
-    }
-    sch = p.schmitt[kk] != 0;
-    dead = p.dead[kk] != 0;
-    if (p.has_stuck) stuck = p.stuck[kk];
-    if (p.has_gain) gain = p.gain[kk];
-  }
-  float gd[12], gw[12];
-#pragma unroll
-  for (int i = 0; i < 12; ++i) { gd[i] = 0.f; gw[i] = 0.f; }
-  if (XT == 2) {   // padding rows of the MFMA staging must read as zero
-    uint32_t* xb = (uint32_t*)(smem + lay.xtb);
-    for (int i = tid; i < 3 * eb * p.tpad; i += blockDim.x) xb[i] = 0u;
-  }
-
-  for (int s = 0; s < p.n_steps; ++s) {
-    const int64_t t = p.step0 + s;
-    const int par = s & 1;
-    Pose* lp = lpose + par * eb * L;
-    Pose* op = opose + par * eb;
-    int* oi = oids + par * eb;
-    unsigned* bw = bitw + par * 2 * eb * words2;
-    unsigned* bwn = bw + eb * words2;
-    // ---- stage link poses (one thread per (env, link)), object poses and ids
-    {
-      const float* ls = p.link_state + (int64_t)s * 13 * EL;
-      for (int idx = tid; idx < eb * L; idx += blockDim.x) {
-        if (e0 + idx / L < p.E) {
-          const int64_t col = (int64_t)e0 * L + idx;
-          float v[13];
-#pragma unroll
-          for (int c = 0; c < 13; ++c) v[c] = ls[c * EL + col];
-          Pose P;
-          quat_to_R(v[3], v[4], v[5], v[6], P.R);
-#pragma unroll
-          for (int i = 0; i < 3; ++i) { P.p[i] = v[i]; P.v[i] = v[7 + i]; P.w[i] = v[10 + i]; }
-          lp[idx] = P;
-        }
-      }
-      for (int idx = tid; idx < eb; idx += blockDim.x) {
-        if (e0 + idx < p.E) {
-          oi[idx] = p.obj_id[(int64_t)s * p.E + e0 + idx];
-          if (OBJ) {
-            const float* os = p.obj_state + (int64_t)s * 13 * p.E;
-            float v[13];
-#pragma unroll
-            for (int c = 0; c < 13; ++c) v[c] = os[c * (int64_t)p.E + e0 + idx];
-            Pose P;
-            quat_to_R(v[3], v[4], v[5], v[6], P.R);
-#pragma unroll
-            for (int i = 0; i < 3; ++i) { P.p[i] = v[i]; P.v[i] = v[7 + i]; P.w[i] = v[10 + i]; }
-            op[idx] = P;
-          }
-        }
-      }
-      for (int idx = tid; idx < 2 * eb * words2; idx += blockDim.x) bw[idx] = 0u;
-    }
-    __syncthreads();
-
-    // ---- clean readout
-    TaxelOut o;
-    if (act) {
-      readout_probe(p, lp[el * L + lk], OBJ ? &op[el] : nullptr, oi[el], ta, tb, o);
-    } else {
-      o.depth = 0.f; o.phi = 0.f; o.prox = 0.f; o.surf = 0.f; o.active = false; o.far = false;
-#pragma unroll
-      for (int i = 0; i < 3; ++i) { o.f[i] = 0.f; o.tau[i] = 0.f; o.mb[i] = 0.f; }
-    }
-    const bool bit = o.depth > p.eta_on;
-    if (act) {
-      const int64_t ok = (int64_t)s * ET + kk;
-      if (p.depth) p.depth[ok] = o.depth;
-      if (p.prox) p.prox[ok] = o.prox;
-      if (p.surfdist) p.surfdist[ok] = o.surf;
-      if (p.ft) {
-        float* f = p.ft + (int64_t)s * 6 * ET + kk;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) { f[c * ET] = o.f[c]; f[(c + 3) * ET] = o.tau[c]; }
-      }
-      if (p.normal) {
-        float* nm = p.normal + (int64_t)s * 3 * ET + kk;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) nm[c * ET] = o.mb[c];
-      }
-      if (bit) atomicOr(&bw[el * words2 + (j >> 5)], 1u << (j & 31));
-    }
-    const bool sums = p.link_sums != nullptr;
-    if (sums && tid < nr) {
-      sv[0 * nr + tid] = o.f[0]; sv[1 * nr + tid] = o.f[1]; sv[2 * nr + tid] = o.f[2];
-      sv[3 * nr + tid] = o.tau[0]; sv[4 * nr + tid] = o.tau[1]; sv[5 * nr + tid] = o.tau[2];
-      sv[6 * nr + tid] = bit ? 1.f : 0.f;
-      sv[7 * nr + tid] = o.depth * tb.z;
-      sv[8 * nr + tid] = o.depth * tb.y;
-      sv[9 * nr + tid] = o.depth * tb.x;
-    }
-    float z[6] = {gain * o.f[0], gain * o.f[1], gain * o.f[2], gain * o.tau[0], gain * o.tau[1], gain * o.tau[2]};
-    if (NOISE && XT == 1) {
-      if (tid < nr) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) xv[c * nr + tid] = z[c];
-      }
-    }
-    __syncthreads();
-    if (p.bits) {
-      for (int idx = tid; idx < eb * W; idx += blockDim.x) {
-        const int e_ = e0 + idx / W;
-        if (e_ < p.E)
-          p.bits[(int64_t)s * p.E * W + (int64_t)e0 * W + idx] =
-              (unsigned long long)bw[2 * idx] | ((unsigned long long)bw[2 * idx + 1] << 32);
-      }
-    }
-    if (sums) link_sums_from_lds(p, sv, nr, e0, p.link_sums + (int64_t)s * 11 * EL);
-
-    if (NOISE) {
-      // ---- spatial crosstalk within the link
-      float zt[6];
-      if (XT == 1) {
-        const float chi = p.chi;
-        const bool hasl = j > la, hasr = j < lb - 1;
-        const float cjj = 1.0f - chi * (float)((int)hasl + (int)hasr);
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-          float acc = cjj * z[c];
-          if (act && hasl) acc = fmaf(chi, xv[c * nr + tid - 1], acc);
-          if (act && hasr) acc = fmaf(chi, xv[c * nr + tid + 1], acc);
-          zt[c] = acc;
-        }
-      } else if (XT == 2) {
-        xtalk_dense_block(p, z, zt, smem + lay.xtb, smem + lay.xtx, el, j, lk, act, e0);
-      } else {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) zt[c] = z[c];
-      }
-      // ---- random streams for this step
-      if (p.drift_sigma != 0.f && ((t & 1) == 0 || s == 0) && act)
-        gauss12(p.key0, p.key1, (uint32_t)e, (uint32_t)j, (uint32_t)(t >> 1), 0u, gd);
-      if (p.white_sigma != 0.f && ((t & 1) == 0 || s == 0) && act)
-        gauss12(p.key0, p.key1, (uint32_t)e, (uint32_t)j, (uint32_t)(t >> 1), 3u, gw);
-      const bool hi = (t & 1) != 0;
-      float fo[6];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        const float x = zt[c];
-        float h = x;
-        if (HY == 1) {
-          const float kap = fabsf(x) > fabsf(Y[c]) ? p.kload : p.kunload;
-          Y[c] = fmaf(kap, x - Y[c], Y[c]);
-          h = Y[c];
-        } else if (HY == 2) {
-          Y[c] = fmaf(p.decay, Y[c], x - XP[c]);
-          XP[c] = x;
-          h = fmaf(p.beta, Y[c], x);
-        }
-        float v = h;
-        if (p.bias != 0.f) v = v + p.bias;
-        if (p.white_sigma != 0.f) v = fmaf(p.white_sigma, hi ? gw[6 + c] : gw[c], v);
-        if (p.drift_sigma != 0.f) {
-          D[c] = fmaf(p.drift_sigma, hi ? gd[6 + c] : gd[c], D[c]);
-          v = v + D[c];
-        }
-        if (p.quant > 0.f) v = p.quant * rintf(v * p.qinv);
-        if (dead) v = stuck;
-        fo[c] = v;
-      }
-      if (act && p.ft_noisy) {
-        float* f = p.ft_noisy + (int64_t)s * 6 * ET + kk;
-#pragma unroll
-        for (int c = 0; c < 6; ++c) f[c * ET] = fo[c];
-      }
-      // ---- noisy contact bit: probe-radius noise, Schmitt hysteresis, dead overwrite
-      float dd = o.depth;
-      if (p.has_radius) {
-        dd = 0.f;
-        if (act && o.active && !o.far) {
-          uint32_t x0 = (uint32_t)e, x1 = (uint32_t)j, x2 = (uint32_t)t, x3 = 6u;
-          philox4x32_10(x0, x1, x2, x3, p.key0, p.key1);
-          const float u = u01(x0);
-          float Rn = ta.w + fmaf(u, p.two_rho, p.neg_rho);
-          Rn = Rn > 0.f ? Rn : 0.f;
-          const float df = Rn - o.phi;
-          dd = df > 0.f ? df : 0.f;
-        }
-      }
-      bool nb = (dd > p.eta_on) || (sch && dd > p.eta_off);
-      if (dead) { nb = false; dd = 0.f; }
-      sch = nb;
-      if (act && nb) atomicOr(&bwn[el * words2 + (j >> 5)], 1u << (j & 31));
-      const bool sums_n = p.link_sums_noisy != nullptr;
-      if (sums_n) {
-        __syncthreads();   // clean reduction has finished reading sv
-      }
-      if (sums_n && tid < nr) {
-        sv[0 * nr + tid] = fo[0]; sv[1 * nr + tid] = fo[1]; sv[2 * nr + tid] = fo[2];
-        sv[3 * nr + tid] = fo[3]; sv[4 * nr + tid] = fo[4]; sv[5 * nr + tid] = fo[5];
-        sv[6 * nr + tid] = nb ? 1.f : 0.f;
-        sv[7 * nr + tid] = dd * tb.z;
-        sv[8 * nr + tid] = dd * tb.y;
-        sv[9 * nr + tid] = dd * tb.x;
-      }
-      __syncthreads();
-      if (p.bits_noisy) {
-        for (int idx = tid; idx < eb * W; idx += blockDim.x) {
-          const int e_ = e0 + idx / W;
-          if (e_ < p.E)
-            p.bits_noisy[(int64_t)s * p.E * W + (int64_t)e0 * W + idx] =
-                (unsigned long long)bwn[2 * idx] | ((unsigned long long)bwn[2 * idx + 1] << 32);
-        }
-      }
-      if (sums_n) link_sums_from_lds(p, sv, nr, e0, p.link_sums_noisy + (int64_t)s * 11 * EL);
-    }
-  }
-  // ---- write the noise state back
-  if (NOISE && act) {
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      if (p.drift_sigma != 0.f) p.drift[c * ET + kk] = D[c];
-      if (HY) p.hyst[c * ET + kk] = Y[c];
-      if (HY == 2) p.hyst_prev[c * ET + kk] = XP[c];
-    }
-    p.schmitt[kk] = sch ? 1 : 0;
-  }
-}
 
 // Episode reset: zero the dynamic state and draw dead flag, stuck value and gain with
 // counter (env, taxel, reset step, 7).
@@ -345,10 +52,14 @@ __global__ void tg_reset_kernel(KParams p, const uint8_t* mask, int64_t step, fl
 struct tg_readout {
   tg_readout_config cfg{};
   int E = 0, L = 0, T = 0, n_obj = 0, W = 0;
-  int eb = 1, threads = 64;
+  int threads = 64, target = 512;
   size_t lds = 0;
-  int xt = 0, hy = 0, noise = 0;
+  std::vector<LinkInfo> links;
+  LinkInfo* d_links = nullptr;
+  int2* d_items = nullptr;
+  int xt = 0, hy = 0, noise = 0, full = 1;
   KParams kp{};
+  KParams* d_kp = nullptr;   // device copy read by the kernels
   std::vector<void*> allocs;
   std::string err;
   float stuck_lo = 0, stuck_span = 0, gain_lo = 1, gain_span = 0;
@@ -373,20 +84,101 @@ hipError_t dalloc(tg_readout* h, T** p, size_t count) {
   return e;
 }
 
-using KernelFn = void (*)(const KParams);
+using KernelFn = void (*)(const KLaunch);
 
-template <int N, int X, int Y, int O>
-KernelFn pick() { return tg_readout_kernel<N, X, Y, O>; }
+template <int N, int X, int Y, int O, int F>
+KernelFn pick() { return tg_link_kernel<N, X, Y, O, F>; }
 
-KernelFn select_kernel(int noise, int xt, int hy, int obj) {
-  if (!noise) return obj ? pick<0, 0, 0, 1>() : pick<0, 0, 0, 0>();
+template <int F>
+KernelFn select_kernel_f(int noise, int xt, int hy, int obj) {
+  if (!noise) return obj ? pick<0, 0, 0, 1, F>() : pick<0, 0, 0, 0, F>();
 #define TG_PICK(X, Y)                                                   \
-  if (xt == X && hy == Y) return obj ? pick<1, X, Y, 1>() : pick<1, X, Y, 0>();
+  if (xt == X && hy == Y) return obj ? pick<1, X, Y, 1, F>() : pick<1, X, Y, 0, F>();
   TG_PICK(0, 0) TG_PICK(0, 1) TG_PICK(0, 2)
   TG_PICK(1, 0) TG_PICK(1, 1) TG_PICK(1, 2)
   TG_PICK(2, 0) TG_PICK(2, 1) TG_PICK(2, 2)
 #undef TG_PICK
   return nullptr;
+}
+
+KernelFn select_kernel(int noise, int xt, int hy, int obj, int full) {
+  return full ? select_kernel_f<1>(noise, xt, hy, obj) : select_kernel_f<0>(noise, xt, hy, obj);
+}
+
+// Work plan: envs per block for each link (about `target` readouts per block), the
+// (link, first env) items sorted by env, the LDS carve-up sized for the largest link.
+tg_status plan_links(tg_readout* h, int target) {
+  const int L = h->L, E = h->E;
+  const int32_t* off = h->cfg.link_taxel_offset;
+  int nthr = 64;
+  for (int l = 0; l < L; ++l) {
+    LinkInfo& li = h->links[l];
+    li.off = off[l];
+    li.n = off[l + 1] - off[l];
+    if (li.n > 512) return TG_ERR_UNSUPPORTED;
+    // envs per block: ~target readouts, at most 36 envs so that the 14 prefetched scalars per env
+    // fit one per lane
+    li.envs = li.n > 0 ? std::max(1, std::min(std::min(E, 36), target / li.n)) : 1;
+    li.nwin = li.n > 0 ? ((li.off + li.n - 1) >> 6) - (li.off >> 6) + 1 : 1;
+    li.nt = (6 * li.envs + 15) / 16;
+    const int n16 = ((li.n + 15) / 16) * 16;
+    li.kp = n16 + 8;
+    li.kpd = n16 + 4;
+    nthr = std::max(nthr, ((li.envs * li.n + 63) / 64) * 64);
+  }
+  h->threads = nthr;
+  // LDS layout: max over links of each region
+  int64_t pose = 0, bits = 0, bt = 0, dt = 0, tax = 0;
+  for (int l = 0; l < L; ++l) {
+    const LinkInfo& li = h->links[l];
+    pose = std::max<int64_t>(pose, li.envs);
+    bits = std::max<int64_t>(bits, (int64_t)li.envs * li.nwin * 2);
+    tax = std::max<int64_t>(tax, (int64_t)li.n * 32);
+    if (h->xt == 2) {
+      bt = std::max<int64_t>(bt, (int64_t)li.nt * 16 * li.kp * 2);
+      dt = std::max<int64_t>(dt, (int64_t)6 * li.envs * li.kpd * 4);
+    }
+  }
+  LinkLds& d = h->kp.lds;
+  int64_t o = 0;
+  d.pose = (int32_t)o; o = align16i(o + 2 * pose * (int64_t)sizeof(Pose));
+  d.opose = (int32_t)o; o = align16i(o + 2 * pose * (int64_t)sizeof(Pose));
+  d.oid = (int32_t)o; o = align16i(o + 2 * pose * 4);
+  d.bits = (int32_t)o; o = align16i(o + 2 * 2 * bits * 4);
+  d.sums = (int32_t)o; o = align16i(o + 10 * (int64_t)nthr * 4);
+  d.xz = (int32_t)o; o = align16i(o + (h->xt == 1 ? 6 * (int64_t)nthr * 4 : 0));
+  d.tax = (int32_t)o; o = align16i(o + tax);
+  h->kp.gtab_lds = h->n_obj <= 256;
+  d.gtab = (int32_t)o; o = align16i(o + (h->kp.gtab_lds ? (int64_t)h->n_obj * (int64_t)sizeof(GridDesc) : 0));
+  d.raw = (int32_t)o; o = align16i(o + 2 * 14 * pose * 4);
+  d.bt = (int32_t)o; o = align16i(o + bt);
+  d.dt = (int32_t)o; o = align16i(o + dt);
+  d.total = (int32_t)o;
+  h->lds = (size_t)o;
+  // items, env-major so that neighbouring blocks share envs (and objects)
+  std::vector<int2> items;
+  std::vector<int> next(L, 0);
+  for (int e0 = 0; e0 < E; ++e0)
+    for (int l = 0; l < L; ++l)
+      if (h->links[l].n > 0 && e0 == next[l]) {
+        items.push_back(make_int2(l, e0));
+        next[l] += h->links[l].envs;
+      }
+  h->kp.n_items = (int32_t)items.size();
+  h->kp.n_items_pad = (int32_t)(((items.size() + 7) / 8) * 8);
+  if (h->d_items) { (void)hipFree(h->d_items); h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), (void*)h->d_items)); }
+  if (h->d_links) { (void)hipFree(h->d_links); h->allocs.erase(std::find(h->allocs.begin(), h->allocs.end(), (void*)h->d_links)); }
+  h->d_items = nullptr;
+  h->d_links = nullptr;
+  hipError_t e = dalloc(h, &h->d_items, items.size());
+  if (e == hipSuccess) e = dalloc(h, &h->d_links, L);
+  if (e == hipSuccess) e = hipMemcpy(h->d_items, items.data(), items.size() * sizeof(int2), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_links, h->links.data(), L * sizeof(LinkInfo), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return TG_ERR_HIP;
+  h->kp.items = h->d_items;
+  h->kp.links = h->d_links;
+  h->target = target;
+  return TG_OK;
 }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -427,7 +219,6 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
   if (cfg->abi_version != TG_ABI_VERSION) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "abi_version mismatch");
   const int E = cfg->num_envs, L = cfg->num_links, T = cfg->num_taxels, NO = cfg->num_objects;
   if (E <= 0 || L <= 0 || T <= 0 || NO <= 0) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "sizes must be positive");
-  if (T > 1024) return fail(nullptr, TG_ERR_UNSUPPORTED, "more than 1024 taxels per env");
   if (!cfg->link_taxel_offset || !cfg->taxel_pos || !cfg->taxel_normal || !cfg->taxel_radius || !cfg->grids)
     return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "NULL host array in config");
   const int32_t* off = cfg->link_taxel_offset;
@@ -579,29 +370,40 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     h->dead_thr = (unsigned long long)std::min(thr, 4294967296.0);
   }
 
-  // launch shape: whole envs per block, at most 1024 threads
-  h->eb = std::max(1, std::min(E, 1024 / T));
-  h->threads = ((h->eb * T + 63) / 64) * 64;
-  k.eb = h->eb;
-  k.tpad = 0;
+  // dense crosstalk blocks, then the work plan (links x env chunks)
+  h->links.assign(L, LinkInfo{});
   if (h->xt == 2) {
-    tg_status st = xt_dense_setup(h->xtd, cfg, h->eb, &h->err);
+    tg_status st = xt_dense_setup(h->xtd, cfg, h->links.data(), &h->err);
     if (st != TG_OK) {
       std::string m = h->err;
       tg_readout_destroy(h);
       return fail(nullptr, st, m);
     }
-    k.xt_afrag = h->xtd.afrag; k.xt_items = h->xtd.items; k.xt_n_items = h->xtd.n_items;
-    k.tpad = h->xtd.tpad; k.xt_poff = h->xtd.poff;
+    k.xt_afrag = h->xtd.afrag;
   }
-  LdsLayout ll = lds_layout(h->eb, L, T, h->W, noise, h->xt, k.tpad);
-  h->lds = ll.total;
+  {
+    tg_status st = plan_links(h, 512);
+    if (st != TG_OK) {
+      tg_readout_destroy(h);
+      return fail(nullptr, st, st == TG_ERR_UNSUPPORTED ? "a link has more than 512 taxels"
+                                                        : "work plan upload failed");
+    }
+  }
   if (h->lds > 160 * 1024) {
     tg_readout_destroy(h);
     return fail(nullptr, TG_ERR_UNSUPPORTED, "LDS footprint exceeds 160 KiB");
   }
-  KernelFn kf = select_kernel(noise, h->xt, h->hy, 0);
-  KernelFn kf1 = select_kernel(noise, h->xt, h->hy, 1);
+  e = dalloc(h, &h->d_kp, 1);
+  if (e == hipSuccess) e = hipMemcpy(h->d_kp, &h->kp, sizeof(KParams), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    tg_readout_destroy(h);
+    return fail(nullptr, TG_ERR_HIP, std::string("parameter upload: ") + hipGetErrorString(e));
+  }
+  h->full = (noise && (nz.white_sigma != 0.f || nz.bias != 0.f || nz.quant_step > 0.f || nz.radius_rho > 0.f ||
+                        !(nz.gain_lo == 1.0f && nz.gain_hi == 1.0f))) ||
+            (om & (TG_OUT_NORMAL | TG_OUT_SURFDIST)) != 0;
+  KernelFn kf = select_kernel(noise, h->xt, h->hy, 0, h->full);
+  KernelFn kf1 = select_kernel(noise, h->xt, h->hy, 1, h->full);
   if (!kf || !kf1) {
     tg_readout_destroy(h);
     return fail(nullptr, TG_ERR_UNSUPPORTED, "no kernel for this noise configuration");
@@ -672,7 +474,8 @@ tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_s
   if (out->link_sums_noisy && !aligned(out->link_sums_noisy, 16))
     return fail(h, TG_ERR_INVALID_ARGUMENT, "link_sums_noisy misaligned");
 
-  KParams k = h->kp;
+  KLaunch k{};
+  k.kc = h->d_kp;
   k.n_steps = n_steps;
   k.step0 = in->step;
   k.link_state = in->link_state;
@@ -682,9 +485,8 @@ tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_s
   k.bits_noisy = (unsigned long long*)out->contact_bits_noisy;
   k.depth = out->depth; k.prox = out->prox; k.surfdist = out->surfdist; k.ft = out->ft; k.ft_noisy = out->ft_noisy;
   k.normal = out->normal; k.link_sums = out->link_sums; k.link_sums_noisy = out->link_sums_noisy;
-  KernelFn kf = select_kernel(h->noise, h->xt, h->hy, in->obj_state ? 1 : 0);
-  const int blocks = (h->E + h->eb - 1) / h->eb;
-  hipLaunchKernelGGL(kf, dim3(blocks), dim3(h->threads), h->lds, (hipStream_t)hip_stream, k);
+  KernelFn kf = select_kernel(h->noise, h->xt, h->hy, in->obj_state ? 1 : 0, h->full);
+  hipLaunchKernelGGL(kf, dim3(h->kp.n_items_pad), dim3(h->threads), h->lds, (hipStream_t)hip_stream, k);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(h, TG_ERR_HIP, std::string("readout launch: ") + hipGetErrorString(e));
   return TG_OK;
@@ -729,7 +531,7 @@ tg_status tg_readout_set_state(tg_readout* h, const void* src_dev, size_t bytes,
 
 tg_status tg_readout_launch_shape(const tg_readout* h, int32_t* envs_per_block, int32_t* threads) {
   if (!h || !envs_per_block || !threads) return TG_ERR_INVALID_ARGUMENT;
-  *envs_per_block = h->eb;
+  *envs_per_block = h->target;
   *threads = h->threads;
   return TG_OK;
 }

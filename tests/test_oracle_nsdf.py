@@ -1,0 +1,135 @@
+"""Pins of the neural-SDF oracle (positional encoding -> 4 x 64 SiLU -> 1): backprop against
+central finite differences, closed forms of degenerate networks, the first Adam step, and a small
+fit that converges."""
+import math
+
+import numpy as np
+
+import oracle
+
+NP = 15681
+H, F = 64, 48
+
+
+def he_init(rng):
+    P = np.zeros(NP)
+    o = 0
+    for fan_in, fan_out in ((F, H), (H, H), (H, H), (H, H)):
+        lim = math.sqrt(6.0 / fan_in)
+        P[o:o + fan_in * fan_out] = rng.uniform(-lim, lim, fan_in * fan_out)
+        o += fan_in * fan_out + fan_out
+    lim = math.sqrt(6.0 / H)
+    P[o:o + H] = rng.uniform(-lim, lim, H)
+    return P
+
+
+def offsets():
+    o, out = 0, []
+    for fan_in in (F, H, H, H):
+        out.append((o, o + fan_in * H))          # (W, b) offsets
+        o += fan_in * H + H
+    out.append((o, o + H))                       # (w5, b5)
+    return out
+
+
+def silu(z):
+    return z / (1 + np.exp(-z))
+
+
+def test_parameter_count():
+    assert oracle.nsdf_num_params() == NP == 48 * 64 + 64 + 3 * (64 * 64 + 64) + 64 + 1
+
+
+def test_loss_gradient_matches_central_differences():
+    rng = np.random.default_rng(0)
+    P = he_init(rng)
+    P[offsets()[0][1]:offsets()[0][1] + H] = rng.normal(0, 0.1, H)     # nonzero biases too
+    x = rng.uniform(-1, 1, (16, 3))
+    t = rng.normal(0, 0.3, 16)
+    _, g = oracle.nsdf_loss_grad(P, x, t)
+    idx = np.concatenate([rng.choice(NP, 200, replace=False), [NP - 1, NP - 2, 0]])
+    h = 1e-6
+    for i in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] += h
+        Pm[i] -= h
+        fd = (oracle.nsdf_loss_grad(Pp, x, t)[0] - oracle.nsdf_loss_grad(Pm, x, t)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_input_gradient_matches_central_differences():
+    rng = np.random.default_rng(1)
+    P = he_init(rng)
+    x = rng.uniform(-1, 1, (40, 3))
+    _, gx = oracle.nsdf_forward(P, x, grad=True)
+    h = 1e-5      # fourth-order stencil: the encoding reaches 2^7 pi, so second-order FD is too coarse
+    f = lambda y: oracle.nsdf_forward(P, y)
+    for d in range(3):
+        e = np.zeros(3); e[d] = h
+        fd = (-f(x + 2 * e) + 8 * f(x + e) - 8 * f(x - e) + f(x - 2 * e)) / (12 * h)
+        np.testing.assert_allclose(gx[:, d], fd, rtol=1e-6, atol=1e-7)
+
+
+def test_single_path_network_closed_form():
+    """Only feature f* feeds hidden unit 0, which is passed on unit 0 to the output: out = silu^4(feat)."""
+    ofs = offsets()
+    for k, s, d in ((0, 0, 0), (3, 1, 2), (7, 0, 1)):
+        P = np.zeros(NP)
+        f = 6 * k + 3 * s + d                   # [sin xyz, cos xyz] per frequency
+        P[ofs[0][0] + 0 * F + f] = 1.0
+        for l in (1, 2, 3):
+            P[ofs[l][0] + 0] = 1.0              # W_l[0][0]
+        P[ofs[4][0]] = 1.0                      # w5[0]
+        x = np.random.default_rng(2).uniform(-1, 1, (20, 3))
+        feat = (np.sin if s == 0 else np.cos)(2 ** k * math.pi * x[:, d])
+        expect = silu(silu(silu(silu(feat))))
+        np.testing.assert_allclose(oracle.nsdf_forward(P, x), expect, rtol=1e-13, atol=1e-15)
+
+
+def test_input_independent_network():
+    """With every weight zero the hidden layers see only their biases: out = b5 + w5 . silu(b4)."""
+    rng = np.random.default_rng(3)
+    P = np.zeros(NP)
+    ofs = offsets()
+    b4 = rng.normal(size=H); w5 = rng.normal(size=H)
+    P[ofs[3][1]:ofs[3][1] + H] = b4
+    P[ofs[4][0]:ofs[4][0] + H] = w5
+    P[ofs[4][1]] = 0.25
+    out, gx = oracle.nsdf_forward(P, rng.uniform(-1, 1, (5, 3)), grad=True)
+    np.testing.assert_allclose(out, 0.25 + w5 @ silu(b4), rtol=1e-14)
+    assert np.all(gx == 0)
+
+
+def test_first_adam_step_is_signed_lr():
+    """From zero moments, bias correction makes the first step lr * g / (|g| + eps)."""
+    rng = np.random.default_rng(4)
+    P = rng.normal(size=100); m = np.zeros(100); v = np.zeros(100)
+    g = rng.normal(size=100)
+    P0 = P.copy()
+    oracle.nsdf_adam(P, m, v, g, 1, lr=1e-3)
+    np.testing.assert_allclose(P0 - P, 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_bf16_forward_tracks_fp64():
+    rng = np.random.default_rng(5)
+    P = he_init(rng)
+    x = rng.uniform(-1, 1, (200, 3))
+    a = oracle.nsdf_forward(P, x)
+    b = oracle.nsdf_forward(P, x, bf16=True)
+    err = np.abs(a - b) / (np.abs(a).mean() + 1e-12)
+    assert err.max() < 0.05 and err.mean() < 0.01
+
+
+def test_small_fit_converges_on_a_sphere():
+    """A few hundred Adam steps on the normalised SDF of a sphere cut the L1 loss several-fold."""
+    rng = np.random.default_rng(6)
+    P = he_init(rng)
+    m = np.zeros(NP); v = np.zeros(NP)
+    losses = []
+    for t in range(1, 301):
+        x = rng.uniform(-1, 1, (64, 3))
+        target = np.linalg.norm(x, axis=1) - 0.5
+        loss, g = oracle.nsdf_loss_grad(P, x, target)
+        oracle.nsdf_adam(P, m, v, g, t, lr=1e-3)
+        losses.append(loss)
+    assert np.mean(losses[-20:]) < 0.25 * np.mean(losses[:5])
