@@ -115,6 +115,15 @@ typedef struct {
   int32_t noise_enabled;
   tg_noise_desc noise;
   uint32_t output_mask;            /* TG_OUT_* bits                                       */
+  /* SDF backend.  0: the grids (App. A.1, sdf backend).  1: per-object neural surrogates
+   * (include/tg_nsdf.h network and parameter layout) with the grid as fallback wherever the
+   * probe centre is outside the object's grid box or |phi_nn| < nsdf_band; the normal comes
+   * from the network's input gradient outside the band.  Mode 1 computes the clean outputs
+   * only (noise_enabled must be 0). */
+  int32_t sdf_mode;
+  float nsdf_band;                 /* [m], >= 0 (mode 1)                                   */
+  const float* nsdf_params;        /* device [num_objects][15681] FP32; read during create
+                                      only (packed into library-owned BF16 images)          */
 } tg_readout_config;
 
 /* Per-step inputs, device, SoA.  For tg_readout_rollout each array holds n_steps

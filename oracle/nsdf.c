@@ -8,8 +8,10 @@
  * Parameters (15681, flat): W1[64][48], b1[64], W2[64][64], b2[64], W3, b3, W4, b4, w5[64], b5.
  *
  * Loss: mean absolute error of out against phi_target / half_extent (L1).  Optimiser: Adam.
- * Everything in FP64; nsdf_forward_bf16 additionally rounds the GEMM operands (weights and the
- * activations entering each layer) to BF16, the way a BF16 MFMA path does.
+ * Everything in FP64.  With bf16 = 1 the forward emulates a BF16 MFMA path: weights and the
+ * activations entering each layer are rounded to BF16, the layer sum (bias included) is kept
+ * wide, and the pre-activation is rounded to BF16 before SiLU (activations are BF16 tensors).
+ * The oracle's own weights, sums and reverse-pass bookkeeping are FP64 throughout.
  */
 #define _GNU_SOURCE
 #include <math.h>
@@ -64,6 +66,7 @@ static double forward1(const double* P, const double* x, double z[4][NS_H], doub
       double s = 0;
       for (int i = 0; i < nin; ++i) s += bf(W[l][o * nin + i], bfl) * bf(a[l][i], bfl);
       s += b[l][o];
+      s = bf(s, bfl);
       z[l][o] = s;
       a[l + 1][o] = s * sigm(s);
     }
@@ -74,7 +77,9 @@ static double forward1(const double* P, const double* x, double z[4][NS_H], doub
   return out;
 }
 
-/* out[n] and, if gx != NULL, d out / d x_hat [n][3] (reverse pass through the network). */
+/* out[n] and, if gx != NULL, d out / d x_hat [n][3] (reverse pass through the network).  With
+ * bf16 = 1 the reverse pass rounds its GEMM operands (weights and dz) to BF16 as well; the
+ * output weights w5, the running gradient and the encoding derivative stay wide. */
 void or_nsdf_forward(const double* P, int64_t n, const double* x, double* out, double* gx, int bf16) {
   const double *W[5], *b[5];
   param_views(P, W, b);
@@ -89,11 +94,11 @@ void or_nsdf_forward(const double* P, int64_t n, const double* x, double* out, d
       double dz[NS_H];
       for (int o = 0; o < NS_H; ++o) {
         const double sg = sigm(z[l][o]);
-        dz[o] = g[o] * sg * (1.0 + z[l][o] * (1.0 - sg));
+        dz[o] = bf(g[o] * sg * (1.0 + z[l][o] * (1.0 - sg)), bf16);
       }
       for (int i = 0; i < nin; ++i) {
         double t = 0;
-        for (int o = 0; o < NS_H; ++o) t += W[l][o * nin + i] * dz[o];
+        for (int o = 0; o < NS_H; ++o) t += bf(W[l][o * nin + i], bf16) * dz[o];
         gn[i] = t;
       }
       for (int i = 0; i < nin; ++i) g[i] = gn[i];
@@ -110,8 +115,12 @@ void or_nsdf_forward(const double* P, int64_t n, const double* x, double* out, d
   }
 }
 
-/* Mean L1 loss over n points and its gradient with respect to every parameter (grad zeroed here). */
-double or_nsdf_loss_grad(const double* P, int64_t n, const double* x, const double* target, double* grad) {
+/* Mean L1 loss over n points and its gradient with respect to every parameter (grad zeroed here).
+ * bf16 = 1 emulates a BF16 MFMA backward: the forward as in or_nsdf_forward, and every GEMM
+ * operand of the backward rounded to BF16 (dz in both the weight and the input gradient, the
+ * layer inputs in the weight gradient, the weights in the input gradient); the output layer
+ * and all sums stay wide. */
+double or_nsdf_loss_grad(const double* P, int64_t n, const double* x, const double* target, double* grad, int bf16) {
   const double *W[5], *b[5];
   param_views(P, W, b);
   double *GW[5], *Gb[5];
@@ -120,7 +129,7 @@ double or_nsdf_loss_grad(const double* P, int64_t n, const double* x, const doub
   double loss = 0;
   for (int64_t s = 0; s < n; ++s) {
     double z[4][NS_H], a[5][NS_H];
-    const double out = forward1(P, x + 3 * s, z, a, 0);
+    const double out = forward1(P, x + 3 * s, z, a, bf16);
     const double r = out - target[s];
     loss += fabs(r);
     const double go = (r > 0 ? 1.0 : (r < 0 ? -1.0 : 0.0)) / (double)n;
@@ -135,14 +144,14 @@ double or_nsdf_loss_grad(const double* P, int64_t n, const double* x, const doub
       double dz[NS_H], gn[NS_H];
       for (int o = 0; o < NS_H; ++o) {
         const double sg = sigm(z[l][o]);
-        dz[o] = g[o] * sg * (1.0 + z[l][o] * (1.0 - sg));
+        dz[o] = bf(g[o] * sg * (1.0 + z[l][o] * (1.0 - sg)), bf16);
         Gb[l][o] += dz[o];
-        for (int i = 0; i < nin; ++i) GW[l][o * nin + i] += dz[o] * a[l][i];
+        for (int i = 0; i < nin; ++i) GW[l][o * nin + i] += dz[o] * bf(a[l][i], bf16);
       }
       if (l > 0) {
         for (int i = 0; i < nin; ++i) {
           double t = 0;
-          for (int o = 0; o < NS_H; ++o) t += W[l][o * nin + i] * dz[o];
+          for (int o = 0; o < NS_H; ++o) t += bf(W[l][o * nin + i], bf16) * dz[o];
           gn[i] = t;
         }
         for (int i = 0; i < nin; ++i) g[i] = gn[i];
@@ -161,5 +170,38 @@ void or_nsdf_adam(double* P, double* m, double* v, const double* g, int64_t np, 
     m[i] = b1 * m[i] + (1 - b1) * g[i];
     v[i] = b2 * v[i] + (1 - b2) * g[i] * g[i];
     P[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+  }
+}
+
+/* Training targets in FP64: the point is clamped into the node-centred grid box
+ * [origin, origin + (n-1) h]^3, phi is the trilinear interpolant of the grid samples there
+ * (App. A.1, sdf backend), and the record is { (q - c) / e, phi / e } with c the box centre and
+ * e = (n-1) h / 2. */
+void or_nsdf_targets(int32_t n, const float* origin, float spacing, const float* values, int64_t count,
+                     const float* pts, double* rec) {
+  const double h = spacing, ext = (double)(n - 1) * h, e = 0.5 * ext;
+  for (int64_t k = 0; k < count; ++k) {
+    double q[3], t[3];
+    int64_t i[3];
+    for (int d = 0; d < 3; ++d) {
+      const double lo = origin[d], hi = (double)origin[d] + ext;
+      double v = pts[3 * k + d];
+      v = v < lo ? lo : (v > hi ? hi : v);
+      q[d] = v;
+      const double u = (v - lo) / h;
+      int64_t ii = (int64_t)floor(u);
+      if (ii > n - 2) ii = n - 2;
+      if (ii < 0) ii = 0;
+      i[d] = ii;
+      t[d] = u - (double)ii;
+    }
+    double phi = 0;
+    for (int c = 0; c < 8; ++c) {
+      const int dx = c & 1, dy = (c >> 1) & 1, dz = c >> 2;
+      const double w = (dx ? t[0] : 1 - t[0]) * (dy ? t[1] : 1 - t[1]) * (dz ? t[2] : 1 - t[2]);
+      phi += w * values[((i[2] + dz) * n + (i[1] + dy)) * n + (i[0] + dx)];
+    }
+    for (int d = 0; d < 3; ++d) rec[4 * k + d] = (q[d] - ((double)origin[d] + e)) / e;
+    rec[4 * k + 3] = phi / e;
   }
 }

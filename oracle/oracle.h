@@ -43,6 +43,12 @@ typedef struct {
   int32_t xtalk_kind;          /* 0 none, 1 banded, 2 dense */
   float xtalk_chi, xtalk_sigma;
   float eta_off;
+  /* SDF backend: 0 = grids; 1 = per-object neural surrogate (or_nsdf_forward with BF16
+   * emulation) wherever the probe centre is inside the grid box and |phi_nn| >= nsdf_band,
+   * the grid elsewhere. */
+  int32_t sdf_mode;
+  float nsdf_band;
+  const double* nsdf_params;   /* [num_objects][15681] */
 } or_problem;
 
 typedef struct {
@@ -87,6 +93,7 @@ int or_run_f32(const or_problem* P, const or_inputs* in, or_outputs* out, or_sta
 int or_run_f64(const or_problem* P, const or_inputs* in, or_outputs* out, or_state* st, int threads);
 int or_dense_xtalk_f64(const or_problem* P, double* out);  /* concat of n_l*n_l, row-major */
 float or_bf16_round(float x);
+void or_nsdf_forward(const double* P, int64_t n, const double* x, double* out, double* gx, int bf16);
 #ifdef __cplusplus
 }
 #endif

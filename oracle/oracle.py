@@ -46,7 +46,8 @@ class OrProblem(C.Structure):
                 ("dt", C.c_float), ("p_dead", C.c_float), ("stuck_lo", C.c_float), ("stuck_hi", C.c_float),
                 ("radius_rho", C.c_float), ("gain_lo", C.c_float), ("gain_hi", C.c_float),
                 ("xtalk_kind", C.c_int32), ("xtalk_chi", C.c_float), ("xtalk_sigma", C.c_float),
-                ("eta_off", C.c_float)]
+                ("eta_off", C.c_float), ("sdf_mode", C.c_int32), ("nsdf_band", C.c_float),
+                ("nsdf_params", C.c_void_p)]
 
 
 class OrInputs(C.Structure):
@@ -108,7 +109,7 @@ class Oracle:
     """Holds one marshalled problem (a scene restricted to a set of envs) and its noise state."""
 
     def __init__(self, scene, envs: Optional[np.ndarray] = None, precision: str = "f32",
-                 grids_override=None):
+                 grids_override=None, nsdf_params=None, nsdf_band: float = 1e-3):
         self.lib = _load()
         self.sc = scene
         self.prec = precision
@@ -153,6 +154,11 @@ class Oracle:
         P.p_dead, P.stuck_lo, P.stuck_hi = nz.p_dead, nz.stuck_lo, nz.stuck_hi
         P.radius_rho, P.gain_lo, P.gain_hi = nz.radius_rho, nz.gain_lo, nz.gain_hi
         P.xtalk_kind, P.xtalk_chi, P.xtalk_sigma, P.eta_off = nz.xtalk_kind, nz.xtalk_chi, nz.xtalk_sigma, nz.eta_off
+        if nsdf_params is not None:      # neural backend: FP32 parameters held as FP64 copies
+            prm = np.ascontiguousarray(np.asarray(nsdf_params, np.float32).astype(np.float64))
+            assert prm.shape == (len(grids), 15681)
+            self._keep.append(prm)
+            P.sdf_mode, P.nsdf_band, P.nsdf_params = 1, float(nsdf_band), prm.ctypes.data
         self.P = P
         E, T = self.E, self.T
         self.state = dict(drift=np.zeros((6, E, T)), hyst=np.zeros((6, E, T)), hyst_prev=np.zeros((6, E, T)),
@@ -188,9 +194,9 @@ class Oracle:
         return out
 
 
-def run_readout(scene, inp, envs=None, precision="f32", threads=0, **kw):
+def run_readout(scene, inp, envs=None, precision="f32", threads=0, nsdf_params=None, nsdf_band=1e-3, **kw):
     """Convenience: fresh oracle (reset at inp.step0) over `envs`, run every step of `inp`."""
-    o = Oracle(scene, envs, precision)
+    o = Oracle(scene, envs, precision, nsdf_params=nsdf_params, nsdf_band=nsdf_band)
     o.reset(None, inp.step0)
     return o.run(inp, threads=threads, **kw)
 
@@ -217,10 +223,12 @@ def _nsdf_lib():
     if not getattr(lib, "_nsdf_ready", False):
         lib.or_nsdf_num_params.restype = C.c_int
         lib.or_nsdf_forward.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
-        lib.or_nsdf_loss_grad.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        lib.or_nsdf_loss_grad.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         lib.or_nsdf_loss_grad.restype = C.c_double
         lib.or_nsdf_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_double,
                                      C.c_double, C.c_double, C.c_double]
+        lib.or_nsdf_targets.argtypes = [C.c_int32, C.c_void_p, C.c_float, C.c_void_p, C.c_int64, C.c_void_p,
+                                        C.c_void_p]
         lib._nsdf_ready = True
     return lib
 
@@ -239,13 +247,14 @@ def nsdf_forward(P, x, grad=False, bf16=False):
     return (out, gx) if grad else out
 
 
-def nsdf_loss_grad(P, x, target):
+def nsdf_loss_grad(P, x, target, bf16=False):
     lib = _nsdf_lib()
     P = np.ascontiguousarray(P, np.float64)
     x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
     t = np.ascontiguousarray(target, np.float64)
     g = np.zeros_like(P)
-    loss = lib.or_nsdf_loss_grad(P.ctypes.data, x.shape[0], x.ctypes.data, t.ctypes.data, g.ctypes.data)
+    loss = lib.or_nsdf_loss_grad(P.ctypes.data, x.shape[0], x.ctypes.data, t.ctypes.data, g.ctypes.data,
+                                  int(bf16))
     return loss, g
 
 
@@ -255,3 +264,15 @@ def nsdf_adam(P, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = np.ascontiguousarray(g, np.float64)
     lib.or_nsdf_adam(P.ctypes.data, m.ctypes.data, v.ctypes.data, g.ctypes.data, P.size, int(t), lr, b1, b2, eps)
+
+
+def nsdf_targets(grid, points):
+    """FP64 training records {x_hat, phi/e} of object-frame points for one grid (synth.Grid)."""
+    lib = _nsdf_lib()
+    pts = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
+    vals = np.ascontiguousarray(grid.values, np.float32)
+    org = np.ascontiguousarray(grid.origin, np.float32)
+    rec = np.zeros((pts.shape[0], 4))
+    lib.or_nsdf_targets(int(grid.n), org.ctypes.data, float(grid.spacing), vals.ctypes.data,
+                        pts.shape[0], pts.ctypes.data, rec.ctypes.data)
+    return rec

@@ -137,6 +137,26 @@ static void SFX(readout)(const or_problem* P, const SFX(pose) * L, const SFX(pos
       return;
     }
     o->surf = phi;
+    if (P->sdf_mode == 1) {
+      /* neural surrogate: x_hat = (q_o - c) / e over the grid box (c = centre, e = half extent,
+       * both rounded to FP32 as the library does), phi_nn = e * out(x_hat); the grid stays in
+       * charge inside the band |phi_nn| < nsdf_band */
+      const float half = 0.5f * ((float)(N - 1) * g->spacing);
+      const float einv = 1.0f / half;
+      double xh[3], out, gxh[3];
+      for (int i = 0; i < 3; ++i) {
+        const REAL c = (REAL)(g->origin[i] + half);
+        xh[i] = (double)((qo[i] - c) * (REAL)einv);
+      }
+      or_nsdf_forward(P->nsdf_params + (int64_t)oid * 15681, 1, xh, &out, gxh, 1);
+      const REAL phin = (REAL)half * (REAL)out;
+      if (!(FABS(phin) < (REAL)P->nsdf_band)) {
+        phi = phin;
+        o->surf = phi;
+        for (int i = 0; i < 3; ++i) grad[i] = (REAL)gxh[i];
+        goto have_sdf;
+      }
+    }
     /* analytic gradient of the same trilinear interpolant (direction only) */
     REAL gx = SFX(lerp)(t[2], SFX(lerp)(t[1], c[1][0][0] - c[0][0][0], c[1][1][0] - c[0][1][0]),
                         SFX(lerp)(t[1], c[1][0][1] - c[0][0][1], c[1][1][1] - c[0][1][1]));
@@ -146,6 +166,7 @@ static void SFX(readout)(const or_problem* P, const SFX(pose) * L, const SFX(pos
                         SFX(lerp)(t[0], c[0][1][1] - c[0][1][0], c[1][1][1] - c[1][1][0]));
     grad[0] = gx; grad[1] = gy; grad[2] = gz;
   }
+have_sdf:
   o->phi = phi;
   /* depth d = [R_j - phi]_+ (App. A.1, SDF backend) */
   REAL diff = Rj - phi;

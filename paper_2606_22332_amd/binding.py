@@ -20,6 +20,7 @@ ABI_VERSION = 1
 TG_OUT_BITS, TG_OUT_DEPTH, TG_OUT_PROX, TG_OUT_FT = 1, 2, 4, 8
 TG_OUT_NOISY, TG_OUT_NORMAL, TG_OUT_SURFDIST, TG_OUT_LINK_SUMS = 16, 32, 64, 128
 OUT_ALL = 255
+NSDF_NUM_PARAMS = 15681
 
 
 class TgError(RuntimeError):
@@ -47,7 +48,8 @@ class TgReadoutConfig(C.Structure):
                 ("grids", C.c_void_p), ("k_n", C.c_float), ("c_n", C.c_float), ("alpha", C.c_float),
                 ("k_t", C.c_float), ("k_w", C.c_float), ("mu", C.c_float), ("prox_range", C.c_float),
                 ("eta_on", C.c_float), ("ft_spring_only", C.c_int32), ("noise_enabled", C.c_int32),
-                ("noise", TgNoiseDesc), ("output_mask", C.c_uint32)]
+                ("noise", TgNoiseDesc), ("output_mask", C.c_uint32), ("sdf_mode", C.c_int32),
+                ("nsdf_band", C.c_float), ("nsdf_params", C.c_void_p)]
 
 
 class TgStepInputs(C.Structure):
@@ -104,7 +106,8 @@ def _stream_ptr(stream) -> Optional[int]:
     return s.cuda_stream
 
 
-def make_config(scene, output_mask: int = OUT_ALL, keep: Optional[list] = None) -> TgReadoutConfig:
+def make_config(scene, output_mask: int = OUT_ALL, keep: Optional[list] = None, nsdf_params=None,
+                nsdf_band: float = 1e-3) -> TgReadoutConfig:
     """Marshal a synthetic scene (paper_2606_22332_amd.synth.Scene) into tg_readout_config.
     Host arrays are kept alive in `keep` until create has copied them."""
     keep = [] if keep is None else keep
@@ -142,6 +145,10 @@ def make_config(scene, output_mask: int = OUT_ALL, keep: Optional[list] = None) 
     if not nz.enabled:
         output_mask &= ~TG_OUT_NOISY
     cfg.output_mask = output_mask
+    if nsdf_params is not None:      # torch float32 [num_objects, 15681] on the device
+        assert nsdf_params.is_cuda and nsdf_params.is_contiguous()
+        assert tuple(nsdf_params.shape) == (len(scene.grids), NSDF_NUM_PARAMS)
+        cfg.sdf_mode, cfg.nsdf_band, cfg.nsdf_params = 1, float(nsdf_band), nsdf_params.data_ptr()
     return cfg
 
 
@@ -166,12 +173,13 @@ def to_device(inp, device="cuda") -> DeviceInputs:
 class Readout:
     """A tg_readout handle plus torch-allocated output buffers for up to `max_steps` steps."""
 
-    def __init__(self, scene, output_mask: int = OUT_ALL, device: str = "cuda"):
+    def __init__(self, scene, output_mask: int = OUT_ALL, device: str = "cuda", nsdf_params=None,
+                 nsdf_band: float = 1e-3):
         import torch
         self.lib = load()
         self.scene = scene
         keep: list = []
-        cfg = make_config(scene, output_mask, keep)
+        cfg = make_config(scene, output_mask, keep, nsdf_params, nsdf_band)
         self.mask = cfg.output_mask
         h = C.c_void_p()
         rc = self.lib.tg_readout_create(C.byref(cfg), C.byref(h))
@@ -281,3 +289,134 @@ def unpack_bits(words: np.ndarray, T: int) -> np.ndarray:
     w = np.ascontiguousarray(words).view(np.uint64)
     b = np.unpackbits(w.view(np.uint8).reshape(w.shape + (8,)), axis=-1, bitorder="little")
     return b.reshape(w.shape[:-1] + (w.shape[-1] * 64,))[..., :T]
+
+
+# ------------------------------------------------------------------------------------------------
+# neural SDF surrogate (include/tg_nsdf.h)
+# ------------------------------------------------------------------------------------------------
+
+
+class TgNsdfConfig(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("num_objects", C.c_int32), ("grids", C.c_void_p)]
+
+
+class TgNsdfTrainParams(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("batch", C.c_int32), ("seed", C.c_uint64)]
+
+
+_nsdf_ready = False
+
+
+def _nsdf_lib() -> C.CDLL:
+    global _nsdf_ready
+    lib = load()
+    if not _nsdf_ready:
+        P, I64 = C.c_void_p, C.c_int64
+        sig = {
+            "tg_nsdf_create": ([P, P], C.c_int),
+            "tg_nsdf_destroy": ([P], C.c_int),
+            "tg_nsdf_last_error": ([P], C.c_char_p),
+            "tg_nsdf_targets": ([P, P, I64, P, P], C.c_int),
+            "tg_nsdf_grad": ([P, P, P, I64, P, P, P], C.c_int),
+            "tg_nsdf_adam": ([P, P, P, P, I64, I64, P, P], C.c_int),
+            "tg_nsdf_train": ([P, P, P, P, P, I64, I64, C.c_int32, P, P, P], C.c_int),
+            "tg_nsdf_query": ([P, P, P, I64, P, P, P, P], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _nsdf_ready = True
+    return lib
+
+
+def train_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, batch=16384, seed=0) -> TgNsdfTrainParams:
+    return TgNsdfTrainParams(lr, beta1, beta2, eps, batch, seed)
+
+
+class Nsdf:
+    """Per-object neural SDF networks over the grids of a scene (or a list of synth.Grid).
+
+    Parameters, Adam moments, samples and outputs are torch tensors on the current device;
+    this class only passes their pointers to the library."""
+
+    def __init__(self, grids):
+        self.lib = _nsdf_lib()
+        self.n_obj = len(grids)
+        keep = []
+        arr = (TgSdfGrid * self.n_obj)()
+        for i, g in enumerate(grids):
+            v = np.ascontiguousarray(g.values, np.float32)
+            keep.append(v)
+            arr[i].n = g.n
+            arr[i].origin[:] = [float(x) for x in g.origin]
+            arr[i].spacing = float(g.spacing)
+            arr[i].values = v.ctypes.data
+        cfg = TgNsdfConfig(ABI_VERSION, self.n_obj, C.cast(arr, C.c_void_p).value)
+        h = C.c_void_p()
+        rc = self.lib.tg_nsdf_create(C.byref(cfg), C.byref(h))
+        if rc != 0:
+            raise TgError(f"tg_nsdf_create: {self.lib.tg_nsdf_last_error(None).decode()}")
+        self.h = h
+
+    def _chk(self, rc, what):
+        if rc != 0:
+            raise TgError(f"{what}: {self.lib.tg_status_string(rc).decode()}: "
+                          f"{self.lib.tg_nsdf_last_error(self.h).decode()}")
+
+    def targets(self, points, samples=None, stream=None):
+        """points: float32 [n_obj, n, 3] object-frame positions -> float32 [n_obj, n, 4] records."""
+        import torch
+        assert points.is_cuda and points.dtype == torch.float32 and points.is_contiguous()
+        n = points.shape[1]
+        if samples is None:
+            samples = torch.empty((self.n_obj, n, 4), dtype=torch.float32, device=points.device)
+        self._chk(self.lib.tg_nsdf_targets(self.h, points.data_ptr(), n, samples.data_ptr(), _stream_ptr(stream)),
+                  "tg_nsdf_targets")
+        return samples
+
+    def grad(self, params, samples, stream=None):
+        import torch
+        n = samples.shape[1]
+        g = torch.empty_like(params)
+        loss = torch.empty(self.n_obj, dtype=torch.float32, device=params.device)
+        self._chk(self.lib.tg_nsdf_grad(self.h, params.data_ptr(), samples.data_ptr(), n, g.data_ptr(),
+                                        loss.data_ptr(), _stream_ptr(stream)), "tg_nsdf_grad")
+        return loss, g
+
+    def adam(self, params, m, v, grad, t, hp: TgNsdfTrainParams, stream=None):
+        self._chk(self.lib.tg_nsdf_adam(params.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(),
+                                        params.numel(), int(t), C.byref(hp), _stream_ptr(stream)), "tg_nsdf_adam")
+
+    def train(self, params, m, v, samples, step0, n_steps, hp: TgNsdfTrainParams, loss=None, stream=None):
+        n = samples.shape[1]
+        lp = loss.data_ptr() if loss is not None else None
+        self._chk(self.lib.tg_nsdf_train(self.h, params.data_ptr(), m.data_ptr(), v.data_ptr(), samples.data_ptr(),
+                                         n, int(step0), int(n_steps), C.byref(hp), lp, _stream_ptr(stream)),
+                  "tg_nsdf_train")
+
+    def query(self, params, offsets, xhat, grad=True, stream=None):
+        """offsets: int64 list/array [n_obj+1] (points grouped by object); xhat: float32 [n, 3] on device."""
+        import torch
+        offs = np.asarray(offsets, np.int64)
+        d_off = torch.from_numpy(offs).to(xhat.device)
+        n = xhat.shape[0]
+        out = torch.empty(n, dtype=torch.float32, device=xhat.device)
+        g = torch.empty((n, 3), dtype=torch.float32, device=xhat.device) if grad else None
+        self._keep = d_off
+        self._chk(self.lib.tg_nsdf_query(self.h, params.data_ptr(), d_off.data_ptr(), int(np.diff(offs).max()),
+                                         xhat.data_ptr(), out.data_ptr(), g.data_ptr() if grad else None,
+                                         _stream_ptr(stream)), "tg_nsdf_query")
+        return (out, g) if grad else out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tg_nsdf_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

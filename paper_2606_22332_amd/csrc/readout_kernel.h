@@ -98,19 +98,9 @@ struct TaxelOut {
   bool active, far;
 };
 
-// Clean readout of one probe; the operation sequence is fixed (see readout_device.h).
-template <class KP>
-__device__ __forceinline__ void readout_probe(KP& p, const GridDesc* gtab, const Pose& Lp, const Pose* Op, int oid,
-                                              float4 ta, float4 tb, TaxelOut& o) {
-  o.depth = 0.f; o.phi = 0.f; o.prox = 0.f; o.surf = 3.402823466e+38f;
-#pragma unroll
-  for (int i = 0; i < 3; ++i) { o.f[i] = 0.f; o.tau[i] = 0.f; o.mb[i] = 0.f; }
-  o.active = false; o.far = false;
-  const float Rj = ta.w;
-  if (oid < 0 || oid >= p.n_obj || !(Rj > 0.f)) return;
-  o.active = true;
-  const float xj[3] = {ta.x, ta.y, ta.z};
-  float q[3], qo[3];
+// Probe centre in the world (q) and object (qo) frames (App. A.1, probe geometry).
+__device__ __forceinline__ void probe_point(const Pose& Lp, const Pose* Op, const float xj[3], float q[3],
+                                            float qo[3]) {
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     q[i] = fmaf(Lp.R[3 * i + 2], xj[2], fmaf(Lp.R[3 * i + 1], xj[1], fmaf(Lp.R[3 * i], xj[0], Lp.p[i])));
@@ -119,9 +109,17 @@ __device__ __forceinline__ void readout_probe(KP& p, const GridDesc* gtab, const
   } else {
     qo[0] = q[0]; qo[1] = q[1]; qo[2] = q[2];
   }
-  GridDesc g;
-  if (p.gtab_lds) g = gtab[oid];
-  else g = p.grids[oid];
+}
+
+// Trilinear grid lookup: far flag, value (at the clamped point when far), the 8 corners and the
+// cell coordinates for the lazily evaluated gradient, and the far-field surface distance.
+struct GridHit {
+  float phi, surf;
+  float c000, c100, c010, c110, c001, c101, c011, c111;
+  float t[3];
+  bool far;
+};
+__device__ __forceinline__ void grid_lookup(const GridDesc& g, const float* grid_vals, const float qo[3], GridHit& h) {
   float u[3];
   bool far = false;
 #pragma unroll
@@ -129,7 +127,7 @@ __device__ __forceinline__ void readout_probe(KP& p, const GridDesc* gtab, const
     u[i] = (qo[i] - g.origin[i]) * g.hinv;
     far |= !(u[i] >= 0.f && u[i] <= g.nm1);
   }
-  float uc[3], t[3];
+  float uc[3];
   int ii[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
@@ -137,26 +135,42 @@ __device__ __forceinline__ void readout_probe(KP& p, const GridDesc* gtab, const
     int k = (int)floorf(uc[i]);
     k = k > g.n - 2 ? g.n - 2 : k;
     ii[i] = k;
-    t[i] = uc[i] - (float)k;
+    h.t[i] = uc[i] - (float)k;
   }
-  const float* G = p.grid_vals + g.offset;
+  const float* G = grid_vals + g.offset;
   const int N = g.n;
   const uint32_t base = ((uint32_t)ii[2] * (uint32_t)N + (uint32_t)ii[1]) * (uint32_t)N + (uint32_t)ii[0];
   const uint32_t sy = (uint32_t)N, sz = (uint32_t)N * (uint32_t)N;
-  const float c000 = G[base], c100 = G[base + 1];
-  const float c010 = G[base + sy], c110 = G[base + sy + 1];
-  const float c001 = G[base + sz], c101 = G[base + sz + 1];
-  const float c011 = G[base + sz + sy], c111 = G[base + sz + sy + 1];
-  const float l00 = lerpf(t[0], c000, c100), l10 = lerpf(t[0], c010, c110);
-  const float l01 = lerpf(t[0], c001, c101), l11 = lerpf(t[0], c011, c111);
-  const float phi = lerpf(t[2], lerpf(t[1], l00, l10), lerpf(t[1], l01, l11));
+  h.c000 = G[base]; h.c100 = G[base + 1];
+  h.c010 = G[base + sy]; h.c110 = G[base + sy + 1];
+  h.c001 = G[base + sz]; h.c101 = G[base + sz + 1];
+  h.c011 = G[base + sz + sy]; h.c111 = G[base + sz + sy + 1];
+  const float* t = h.t;
+  const float l00 = lerpf(t[0], h.c000, h.c100), l10 = lerpf(t[0], h.c010, h.c110);
+  const float l01 = lerpf(t[0], h.c001, h.c101), l11 = lerpf(t[0], h.c011, h.c111);
+  h.phi = lerpf(t[2], lerpf(t[1], l00, l10), lerpf(t[1], l01, l11));
+  h.far = far;
   if (far) {
     const float du0 = u[0] - uc[0], du1 = u[1] - uc[1], du2 = u[2] - uc[2];
-    o.far = true;
-    o.surf = phi + sqrtf(fmaf(du2, du2, fmaf(du1, du1, du0 * du0))) * g.spacing;
-    return;
+    h.surf = h.phi + sqrtf(fmaf(du2, du2, fmaf(du1, du1, du0 * du0))) * g.spacing;
+  } else {
+    h.surf = h.phi;
   }
-  o.surf = phi;
+}
+// Gradient direction of the trilinear interpolant (the bilinear blend of the edge differences).
+__device__ __forceinline__ void grid_grad(const GridHit& h, float& gx, float& gy, float& gz) {
+  const float* t = h.t;
+  gx = lerpf(t[2], lerpf(t[1], h.c100 - h.c000, h.c110 - h.c010), lerpf(t[1], h.c101 - h.c001, h.c111 - h.c011));
+  gy = lerpf(t[2], lerpf(t[0], h.c010 - h.c000, h.c110 - h.c100), lerpf(t[0], h.c011 - h.c001, h.c111 - h.c101));
+  gz = lerpf(t[1], lerpf(t[0], h.c001 - h.c000, h.c101 - h.c100), lerpf(t[0], h.c011 - h.c010, h.c111 - h.c110));
+}
+
+// Everything after the SDF: depth, proximity, and for d > 0 the contact normal (from the
+// gradient direction `grad`, evaluated only then), relative velocity and force/torque
+// (App. A, ContactDepthProbe, KinematicTaxel, ProximityTaxel).
+template <class KP, class GradFn>
+__device__ __forceinline__ void probe_finish(KP& p, const Pose& Lp, const Pose* Op, const float xj[3], float Rj,
+                                             float4 tb, const float q[3], float phi, GradFn grad, TaxelOut& o) {
   o.phi = phi;
   const float diff = Rj - phi;
   const float d = diff > 0.f ? diff : 0.f;
@@ -167,10 +181,8 @@ __device__ __forceinline__ void readout_probe(KP& p, const GridDesc* gtab, const
     o.prox = (w * w) * (3.0f - 2.0f * w);
   }
   if (!(d > 0.f)) return;
-  // contact normal: analytic gradient of the same trilinear interpolant
-  const float gx = lerpf(t[2], lerpf(t[1], c100 - c000, c110 - c010), lerpf(t[1], c101 - c001, c111 - c011));
-  const float gy = lerpf(t[2], lerpf(t[0], c010 - c000, c110 - c100), lerpf(t[0], c011 - c001, c111 - c101));
-  const float gz = lerpf(t[1], lerpf(t[0], c001 - c000, c101 - c100), lerpf(t[0], c011 - c010, c111 - c110));
+  float gx, gy, gz;
+  grad(gx, gy, gz);
   const float n2 = fmaf(gz, gz, fmaf(gy, gy, gx * gx));
   float m[3], mb[3];
   if (n2 > 0.f) {
@@ -241,6 +253,37 @@ __device__ __forceinline__ void readout_probe(KP& p, const GridDesc* gtab, const
   }
 #pragma unroll
   for (int i = 0; i < 3; ++i) { o.f[i] = f[i]; o.tau[i] = tau[i]; o.mb[i] = mb[i]; }
+}
+
+__device__ __forceinline__ void taxel_out_clear(TaxelOut& o) {
+  o.depth = 0.f; o.phi = 0.f; o.prox = 0.f; o.surf = 3.402823466e+38f;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { o.f[i] = 0.f; o.tau[i] = 0.f; o.mb[i] = 0.f; }
+  o.active = false; o.far = false;
+}
+
+// Clean readout of one probe on the grid SDF; the operation sequence is fixed (see readout_device.h).
+template <class KP>
+__device__ __forceinline__ void readout_probe(KP& p, const GridDesc* gtab, const Pose& Lp, const Pose* Op, int oid,
+                                              float4 ta, float4 tb, TaxelOut& o) {
+  taxel_out_clear(o);
+  const float Rj = ta.w;
+  if (oid < 0 || oid >= p.n_obj || !(Rj > 0.f)) return;
+  o.active = true;
+  const float xj[3] = {ta.x, ta.y, ta.z};
+  float q[3], qo[3];
+  probe_point(Lp, Op, xj, q, qo);
+  GridDesc g;
+  if (p.gtab_lds) g = gtab[oid];
+  else g = p.grids[oid];
+  GridHit h;
+  grid_lookup(g, p.grid_vals, qo, h);
+  o.surf = h.surf;
+  if (h.far) {
+    o.far = true;
+    return;
+  }
+  probe_finish(p, Lp, Op, xj, Rj, tb, q, h.phi, [&](float& gx, float& gy, float& gz) { grid_grad(h, gx, gy, gz); }, o);
 }
 
 }  // namespace tg

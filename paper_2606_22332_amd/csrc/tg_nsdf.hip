@@ -1,0 +1,606 @@
+// Neural SDF surrogate: packing, training targets, gradient, Adam, fused training and
+// evaluation kernels behind include/tg_nsdf.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tg_nsdf.h"
+#include "nsdf_device.h"
+#include "nsdf_host.h"
+
+using namespace tg;
+using namespace tg::nsdf;
+
+namespace {
+thread_local std::string g_nsdf_create_error;
+constexpr int NT = 256;  // threads per workgroup: four waves
+
+struct BoxDesc {      // per object: grid + normalisation of its box
+  GridDesc grid;
+  float centre[3];
+  float half;         // e = (n-1) * spacing / 2
+  float half_inv;     // RN(1 / e)
+  float hi[3];        // far corner of the box
+};
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// packing: FP32 parameters -> per-object image (BF16 fragments + FP32 tail)
+// ------------------------------------------------------------------------------------------------
+__global__ void nsdf_pack_kernel(const float* __restrict__ P, int n_obj, uint32_t* __restrict__ img) {
+  const int o = blockIdx.y;
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= n_obj || w >= IMG_WORDS) return;
+  img[(size_t)o * IMG_WORDS + w] = image_word(P + (size_t)o * NPARAM, w);
+}
+
+// ------------------------------------------------------------------------------------------------
+// training targets: clamp into the box, trilinear grid value, normalise
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ float grid_value(const GridDesc& gd, const float* __restrict__ vals, const float* q) {
+  float t[3];
+  int i[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float u = (q[d] - gd.origin[d]) * gd.hinv;
+    const float uc = fminf(fmaxf(u, 0.0f), gd.nm1);
+    const int ii = min((int)floorf(uc), gd.n - 2);
+    i[d] = ii;
+    t[d] = uc - (float)ii;
+  }
+  const int n = gd.n;
+  const float* c = vals + gd.offset + ((int64_t)i[2] * n + i[1]) * n + i[0];
+  const int sy = n, sz = n * n;
+  const float c000 = c[0], c100 = c[1], c010 = c[sy], c110 = c[sy + 1];
+  const float c001 = c[sz], c101 = c[sz + 1], c011 = c[sz + sy], c111 = c[sz + sy + 1];
+  const float x00 = lerpf(t[0], c000, c100), x10 = lerpf(t[0], c010, c110);
+  const float x01 = lerpf(t[0], c001, c101), x11 = lerpf(t[0], c011, c111);
+  const float y0 = lerpf(t[1], x00, x10), y1 = lerpf(t[1], x01, x11);
+  return lerpf(t[2], y0, y1);
+}
+
+__global__ void nsdf_targets_kernel(const BoxDesc* __restrict__ boxes, const float* __restrict__ vals,
+                                    const float* __restrict__ pts, int64_t n, float4* __restrict__ out) {
+  const int o = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const BoxDesc b = boxes[o];
+  const int64_t k = (int64_t)o * n + i;
+  float q[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) q[d] = fminf(fmaxf(pts[3 * k + d], b.grid.origin[d]), b.hi[d]);
+  const float phi = grid_value(b.grid, vals, q);
+  out[k] = make_float4((q[0] - b.centre[0]) * b.half_inv, (q[1] - b.centre[1]) * b.half_inv,
+                       (q[2] - b.centre[2]) * b.half_inv, phi * b.half_inv);
+}
+
+// ------------------------------------------------------------------------------------------------
+// loss gradient and training: one workgroup per object, four waves, wave w owns hidden layer w
+// ------------------------------------------------------------------------------------------------
+// A round takes 64 records, one tile of 16 per wave.  Each wave runs its tile forward and back
+// through the network (input gradients on MFMA with the transposed fragments) and stages, for
+// every layer, dz (BF16) and the layer's input activations (BF16) in LDS as [feature][sample].
+// After a barrier, the owner of layer l contracts dz_l with the inputs of layer l over the 64
+// samples (16x16x32 MFMA, K = samples of two tiles), so the weight gradient of each layer lives in
+// one wave's accumulators for the whole step.  Bias gradients come from the same staged dz; the
+// output layer's gradient is reduced through a small LDS buffer.
+namespace {
+
+constexpr int SROW = 20;                    // staging row: 16 samples + pad (u16), 40 bytes
+constexpr int STAGE_U16 = 64 * SROW;        // one [64 feature][16 sample] buffer
+constexpr int STAGE_BYTES = 4 * 4 * 2 * STAGE_U16 * 2;   // [wave][layer][dz | act]
+constexpr int RED_FLOATS = 68;              // dw5[64], db5, loss
+constexpr int LDS_FIT = IMG_BYTES + STAGE_BYTES + RED_FLOATS * 4;
+
+__device__ __forceinline__ uint16_t* stage_buf(uint8_t* smem, int wave, int l, int which) {
+  return (uint16_t*)(smem + IMG_BYTES) + ((wave * 4 + l) * 2 + which) * STAGE_U16;
+}
+
+// Stage 16 values held in chain layout (B fragments b[2], lane group g, sample s) as rows of a
+// [feature][sample] buffer.  pe = true: the encoding's own feature order (48 rows).
+__device__ __forceinline__ void stage_frags(uint16_t* buf, const u32x4 b[2], int g, int s, bool pe) {
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const uint32_t w = b[kt][it >> 1];
+      const uint16_t v = (uint16_t)((it & 1) ? (w >> 16) : (w & 0xffffu));
+      int row;
+      if (pe) {
+        if (it >= 6) continue;
+        row = 6 * (4 * kt + g) + it;
+      } else {
+        row = 32 * kt + chain_k(g, it);
+      }
+      buf[row * SROW + s] = v;
+    }
+}
+// Eight samples of one feature row: four from each of two tiles (K order of a 16x16x32 MFMA).
+__device__ __forceinline__ u32x4 stage_pair(const uint16_t* b0, const uint16_t* b1, int row, int g) {
+  const u32x2 x = *(const u32x2*)(b0 + row * SROW + 4 * g);
+  const u32x2 y = *(const u32x2*)(b1 + row * SROW + 4 * g);
+  return u32x4{x[0], x[1], y[0], y[1]};
+}
+
+__device__ __forceinline__ float bf_sum8(u32x4 v) {
+  return (bf_lo(v[0]) + bf_hi(v[0])) + (bf_lo(v[1]) + bf_hi(v[1])) + (bf_lo(v[2]) + bf_hi(v[2])) +
+         (bf_lo(v[3]) + bf_hi(v[3]));
+}
+
+// Forward and backward of this wave's tile; stages dz and layer inputs of every layer.
+__device__ __forceinline__ void tile_backprop(const Img& im, uint8_t* smem, int wave, int lane, float4 rec, bool valid,
+                                              float inv_n, float dw5[4][4], float& db5, float& loss) {
+  const int g = lane >> 4, s = lane & 15;
+  uint32_t z[4][8];
+  u32x4 pe[2];
+  float a4[4][4];
+  const float out = forward_tile(im, lane, rec.x, rec.y, rec.z, z, pe, a4);
+  const float r = out - rec.w;
+  const float go = valid ? ((r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) * inv_n) : 0.f;
+  if (g == 0 && valid) {
+    loss += fabsf(r);
+    db5 += go;
+  }
+  float gr[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      dw5[m][q] = fmaf(go, a4[m][q], dw5[m][q]);
+      gr[m][q] = go * im.tail[256 + 16 * m + 4 * g + q];
+    }
+#pragma unroll
+  for (int l = 3; l >= 0; --l) {
+    __builtin_amdgcn_sched_barrier(0);
+    u32x4 db[2], ain[2];
+    float dz[4][4];
+    dz_frags(gr, z[l], db, dz);
+    if (l == 0) {
+      ain[0] = pe[0];
+      ain[1] = pe[1];
+    } else {
+      act_frags(z[l - 1], ain);
+    }
+    stage_frags(stage_buf(smem, wave, l, 0), db, g, s, false);
+    stage_frags(stage_buf(smem, wave, l, 1), ain, g, s, l == 0);
+    if (l > 0) {
+      f32x4 o[4];
+      layer_bwd<4>(im, l, lane, db, o);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) gr[m][q] = o[m][q];
+    }
+  }
+}
+
+// Weight and bias gradient of layer L over the four staged tiles (owner wave only).
+__device__ __forceinline__ void owner_wgrad(uint8_t* smem, int L, int lane, f32x4 acc[4][4], float dbp[4]) {
+  const int g = lane >> 4, s = lane & 15;
+  const int nin = L == 0 ? 3 : 4;
+#pragma unroll
+  for (int pr = 0; pr < 2; ++pr) {
+    const uint16_t* d0 = stage_buf(smem, 2 * pr, L, 0);
+    const uint16_t* d1 = stage_buf(smem, 2 * pr + 1, L, 0);
+    const uint16_t* a0 = stage_buf(smem, 2 * pr, L, 1);
+    const uint16_t* a1 = stage_buf(smem, 2 * pr + 1, L, 1);
+    u32x4 A[4], B[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      A[m] = stage_pair(d0, d1, 16 * m + s, g);
+      dbp[m] += bf_sum8(A[m]);
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+      if (n < nin) B[n] = stage_pair(a0, a1, 16 * n + s, g);
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n)
+        if (n < nin) acc[m][n] = mfma32(A[m], B[n], acc[m][n]);
+  }
+}
+
+__device__ __forceinline__ void adam_one(float& p, float& m, float& v, float g, float lr, float b1, float b2,
+                                         float eps, float c1, float c2) {
+  m = fmaf(b1, m, (1.0f - b1) * g);
+  v = fmaf(b2, v, (1.0f - b2) * (g * g));
+  p = p - lr * (m / c1) / (sqrtf(v / c2) + eps);
+}
+
+struct FitArgs {
+  float* P;                 // [n_obj][NPARAM] FP32 parameters (updated when training)
+  float* M;                 // Adam moments (training)
+  float* V;
+  const float4* samples;    // [n_obj][n] records
+  int64_t n;
+  float* grad;              // gradient output (gradient mode)
+  float* loss;              // gradient mode: [n_obj]; training: [n_steps][n_obj] or null
+  int64_t step0;
+  int n_steps, n_obj, batch;
+  float lr, b1, b2, eps;
+  uint32_t key0, key1;
+};
+
+}  // namespace
+
+template <int TRAIN>
+__global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int o = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, s = lane & 15;
+  const int L = wave;                                  // layer owned by this wave
+  const int nin = L == 0 ? F : H;
+  float* red = (float*)(smem + IMG_BYTES + STAGE_BYTES);
+  float* Po = a.P + (size_t)o * NPARAM;
+  const float4* So = a.samples + (size_t)o * a.n;
+  for (int w = tid; w < IMG_WORDS; w += NT) ((uint32_t*)smem)[w] = image_word(Po, w);
+  const Img im = img_at(smem);
+  const int64_t per_step = TRAIN ? a.batch : a.n;
+  const float inv_n = 1.0f / (float)per_step;
+  const int rounds = (int)((per_step + 63) / 64);
+  const int n_steps = TRAIN ? a.n_steps : 1;
+  for (int it = 0; it < n_steps; ++it) {
+    const int64_t step = a.step0 + 1 + it;
+    if (tid < RED_FLOATS) red[tid] = 0.f;
+    __syncthreads();
+    f32x4 acc[4][4];
+    float dbp[4], dw5[4][4], db5 = 0.f, lossp = 0.f;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      dbp[m] = 0.f;
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+        dw5[m][n] = 0.f;
+      }
+    }
+    for (int rd = 0; rd < rounds; ++rd) {
+      const int64_t j = (int64_t)rd * 64 + wave * 16 + s;
+      bool valid;
+      int64_t idx;
+      if (TRAIN) {
+        uint32_t x0 = (uint32_t)o, x1 = (uint32_t)step, x2 = (uint32_t)(j >> 2), x3 = 8u;
+        philox4x32_10(x0, x1, x2, x3, a.key0, a.key1);
+        const uint32_t wsel = (j & 3) == 0 ? x0 : ((j & 3) == 1 ? x1 : ((j & 3) == 2 ? x2 : x3));
+        idx = (int64_t)(((uint64_t)wsel * (uint64_t)a.n) >> 32);
+        valid = true;
+      } else {
+        idx = j;
+        valid = j < a.n;
+      }
+      const float4 rec = valid ? So[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+      tile_backprop(im, smem, wave, lane, rec, valid, inv_n, dw5, db5, lossp);
+      __syncthreads();
+      owner_wgrad(smem, L, lane, acc, dbp);
+      __syncthreads();
+    }
+    // Gradient of the step into LDS (the staging area is free now): owners write their layer,
+    // the output layer is reduced over lanes and waves.
+    float* Gl = (float*)(smem + IMG_BYTES);
+    if (tid < H + 1) Gl[W5_OFF + tid] = 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        if (L == 0 && n == 3) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Gl[W_OFF[L] + (16 * m + 4 * g + q) * nin + 16 * n + s] = acc[m][n][q];
+      }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      float v = dbp[m];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (g == 0) Gl[B_OFF[L] + 16 * m + s] = v;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float v = dw5[m][q];
+        v += __shfl_xor(v, 8);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 1);
+        if (s == 0) atomicAdd(&Gl[W5_OFF + 16 * m + 4 * g + q], v);
+      }
+    {
+      float v = db5, w = lossp;
+#pragma unroll
+      for (int k = 32; k >= 1; k >>= 1) {
+        v += __shfl_xor(v, k);
+        w += __shfl_xor(w, k);
+      }
+      if (lane == 0) {
+        atomicAdd(&Gl[B5_OFF], v);
+        atomicAdd(&red[65], w);
+      }
+    }
+    __syncthreads();
+    if (!TRAIN) {
+      float* G = a.grad + (size_t)o * NPARAM;
+      for (int i = tid; i < NPARAM; i += NT) G[i] = Gl[i];
+      if (a.loss && tid == 0) a.loss[o] = red[65] * inv_n;
+    } else {
+      float* Mo = a.M + (size_t)o * NPARAM;
+      float* Vo = a.V + (size_t)o * NPARAM;
+      const float c1 = (float)(1.0 - pow((double)a.b1, (double)step));
+      const float c2 = (float)(1.0 - pow((double)a.b2, (double)step));
+      float* tail = (float*)(smem + FWD_BYTES + BWD_BYTES);
+#pragma unroll 1
+      for (int i = tid; i < NPARAM; i += NT) {
+        float p = Po[i], mm = Mo[i], vv = Vo[i];
+        adam_one(p, mm, vv, Gl[i], a.lr, a.b1, a.b2, a.eps, c1, c2);
+        Po[i] = p;
+        Mo[i] = mm;
+        Vo[i] = vv;
+        int l = -1, oo = 0, in = 0;
+        if (i < B_OFF[0]) { l = 0; oo = i / F; in = i - oo * F; }
+        else if (i >= W_OFF[1] && i < B_OFF[1]) { l = 1; oo = (i - W_OFF[1]) >> 6; in = (i - W_OFF[1]) & 63; }
+        else if (i >= W_OFF[2] && i < B_OFF[2]) { l = 2; oo = (i - W_OFF[2]) >> 6; in = (i - W_OFF[2]) & 63; }
+        else if (i >= W_OFF[3] && i < B_OFF[3]) { l = 3; oo = (i - W_OFF[3]) >> 6; in = (i - W_OFF[3]) & 63; }
+        if (l >= 0) {
+          int fo, bo;
+          weight_slots(l, oo, in, fo, bo);
+          const uint16_t h16 = (uint16_t)bf16_bits(p);
+          *(uint16_t*)(smem + fo) = h16;
+          *(uint16_t*)(smem + bo) = h16;
+        } else {
+          int t;
+          if (i == B5_OFF) t = 320;
+          else if (i >= W5_OFF) t = 256 + (i - W5_OFF);
+          else if (i >= B_OFF[3]) t = 192 + (i - B_OFF[3]);
+          else if (i >= B_OFF[2]) t = 128 + (i - B_OFF[2]);
+          else if (i >= B_OFF[1]) t = 64 + (i - B_OFF[1]);
+          else t = i - B_OFF[0];
+          tail[t] = p;
+        }
+      }
+      if (a.loss && tid == 0) a.loss[(size_t)it * a.n_obj + o] = red[65] * inv_n;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void nsdf_adam_kernel(float* __restrict__ P, float* __restrict__ M, float* __restrict__ V,
+                                 const float* __restrict__ Gr, int64_t count, float lr, float b1, float b2, float eps,
+                                 float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  float p = P[i], m = M[i], v = V[i];
+  adam_one(p, m, v, Gr[i], lr, b1, b2, eps, c1, c2);
+  P[i] = p;
+  M[i] = m;
+  V[i] = v;
+}
+
+// Evaluation: one workgroup per (object, chunk of 64*k points), image of that object in LDS.
+constexpr int QUERY_TILES_PER_WAVE = 8;
+__global__ __launch_bounds__(NT) void nsdf_query_kernel(const uint32_t* __restrict__ images,
+                                                        const int64_t* __restrict__ offsets,
+                                                        const float* __restrict__ xhat, float* __restrict__ out,
+                                                        float* __restrict__ grad) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int o = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t beg = offsets[o], end = offsets[o + 1];
+  const int64_t chunk = (int64_t)blockIdx.x * (4 * 16 * QUERY_TILES_PER_WAVE);
+  if (beg + chunk >= end) return;  // uniform over the workgroup
+  uint32_t* img = (uint32_t*)smem;
+  const uint32_t* src = images + (size_t)o * IMG_WORDS;
+  for (int w = tid; w < IMG_WORDS; w += NT) img[w] = src[w];
+  __syncthreads();
+  const Img im = img_at(smem);
+  for (int tt = 0; tt < QUERY_TILES_PER_WAVE; ++tt) {
+    const int64_t i = beg + chunk + ((int64_t)(wave * QUERY_TILES_PER_WAVE + tt) * 16) + (lane & 15);
+    if (beg + chunk + (int64_t)(wave * QUERY_TILES_PER_WAVE + tt) * 16 >= end) break;  // wave-uniform
+    const bool valid = i < end;
+    float x0 = 0.f, x1 = 0.f, x2 = 0.f;
+    if (valid) {
+      x0 = xhat[3 * i];
+      x1 = xhat[3 * i + 1];
+      x2 = xhat[3 * i + 2];
+    }
+    uint32_t z[4][8];
+    u32x4 pe[2];
+    float a4[4][4];
+    const float y = forward_tile(im, lane, x0, x1, x2, z, pe, a4);
+    float gx[3] = {0.f, 0.f, 0.f};
+    if (grad) input_grad_tile(im, lane, x0, x1, x2, z, gx);
+    if (valid && lane < 16) {
+      out[i] = y;
+      if (grad) {
+        grad[3 * i] = gx[0];
+        grad[3 * i + 1] = gx[1];
+        grad[3 * i + 2] = gx[2];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// host side
+// ------------------------------------------------------------------------------------------------
+struct tg_nsdf {
+  int n_obj = 0;
+  BoxDesc* d_boxes = nullptr;
+  float* d_vals = nullptr;
+  uint32_t* d_img = nullptr;
+  std::string err;
+};
+
+namespace {
+tg_status nfail(tg_nsdf* h, tg_status s, const std::string& msg) {
+  if (h) h->err = msg; else g_nsdf_create_error = msg;
+  return s;
+}
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+}  // namespace
+
+hipError_t nsdf_pack_images(const float* params, int n_obj, uint32_t* images, hipStream_t stream) {
+  hipLaunchKernelGGL(nsdf_pack_kernel, dim3((IMG_WORDS + 255) / 256, n_obj), dim3(256), 0, stream, params, n_obj,
+                     images);
+  return hipGetLastError();
+}
+
+extern "C" {
+
+tg_status tg_nsdf_create(const tg_nsdf_config* cfg, tg_nsdf** out) {
+  if (!out) return nfail(nullptr, TG_ERR_INVALID_ARGUMENT, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return nfail(nullptr, TG_ERR_INVALID_ARGUMENT, "cfg is NULL");
+  if (cfg->abi_version != TG_ABI_VERSION) return nfail(nullptr, TG_ERR_INVALID_ARGUMENT, "abi_version mismatch");
+  if (cfg->num_objects < 1 || !cfg->grids) return nfail(nullptr, TG_ERR_INVALID_ARGUMENT, "no objects");
+  std::vector<BoxDesc> boxes(cfg->num_objects);
+  int64_t total = 0;
+  for (int o = 0; o < cfg->num_objects; ++o) {
+    const tg_sdf_grid& g = cfg->grids[o];
+    if (g.n < 2 || !(g.spacing > 0.f) || !g.values)
+      return nfail(nullptr, TG_ERR_INVALID_ARGUMENT, "grid " + std::to_string(o) + " invalid");
+    BoxDesc& b = boxes[o];
+    for (int d = 0; d < 3; ++d) b.grid.origin[d] = g.origin[d];
+    b.grid.spacing = g.spacing;
+    b.grid.hinv = 1.0f / g.spacing;
+    b.grid.nm1 = (float)(g.n - 1);
+    b.grid.n = g.n;
+    b.grid.pad = 0;
+    b.grid.offset = total;
+    const float ext = (float)(g.n - 1) * g.spacing;
+    b.half = 0.5f * ext;
+    b.half_inv = 1.0f / b.half;
+    for (int d = 0; d < 3; ++d) {
+      b.centre[d] = g.origin[d] + b.half;
+      b.hi[d] = g.origin[d] + ext;
+    }
+    total += (int64_t)g.n * g.n * g.n;
+  }
+  tg_nsdf* h = new (std::nothrow) tg_nsdf();
+  if (!h) return nfail(nullptr, TG_ERR_OUT_OF_MEMORY, "host allocation failed");
+  h->n_obj = cfg->num_objects;
+  if (hipMalloc(&h->d_boxes, sizeof(BoxDesc) * boxes.size()) != hipSuccess ||
+      hipMalloc(&h->d_vals, sizeof(float) * total) != hipSuccess ||
+      hipMalloc(&h->d_img, (size_t)IMG_BYTES * h->n_obj) != hipSuccess) {
+    tg_nsdf_destroy(h);
+    return nfail(nullptr, TG_ERR_OUT_OF_MEMORY, "device allocation failed");
+  }
+  hipError_t e = hipMemcpy(h->d_boxes, boxes.data(), sizeof(BoxDesc) * boxes.size(), hipMemcpyHostToDevice);
+  for (int o = 0; o < cfg->num_objects && e == hipSuccess; ++o) {
+    const tg_sdf_grid& g = cfg->grids[o];
+    e = hipMemcpy(h->d_vals + boxes[o].grid.offset, g.values, sizeof(float) * (size_t)g.n * g.n * g.n,
+                  hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    tg_nsdf_destroy(h);
+    return nfail(nullptr, TG_ERR_HIP, std::string("upload: ") + hipGetErrorString(e));
+  }
+  *out = h;
+  return TG_OK;
+}
+
+tg_status tg_nsdf_destroy(tg_nsdf* h) {
+  if (!h) return TG_OK;
+  if (h->d_boxes) (void)hipFree(h->d_boxes);
+  if (h->d_vals) (void)hipFree(h->d_vals);
+  if (h->d_img) (void)hipFree(h->d_img);
+  delete h;
+  return TG_OK;
+}
+
+const char* tg_nsdf_last_error(const tg_nsdf* h) { return h ? h->err.c_str() : g_nsdf_create_error.c_str(); }
+
+tg_status tg_nsdf_targets(tg_nsdf* h, const float* points, int64_t n, float* samples, void* stream) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  if (!points || !samples || n < 1) return nfail(h, TG_ERR_INVALID_ARGUMENT, "targets: null pointer or n < 1");
+  if (!aligned16(samples)) return nfail(h, TG_ERR_INVALID_ARGUMENT, "targets: samples not 16-byte aligned");
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)h->n_obj);
+  hipLaunchKernelGGL(nsdf_targets_kernel, grid, dim3(256), 0, (hipStream_t)stream, h->d_boxes, h->d_vals, points, n,
+                     (float4*)samples);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+}
+
+tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, int64_t n, float* grad, float* loss,
+                       void* stream) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  if (!params || !samples || !grad || n < 1) return nfail(h, TG_ERR_INVALID_ARGUMENT, "grad: null pointer or n < 1");
+  if (!aligned16(samples)) return nfail(h, TG_ERR_INVALID_ARGUMENT, "grad: samples not 16-byte aligned");
+  hipError_t e = hipFuncSetAttribute((const void*)nsdf_fit_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     LDS_FIT);
+  if (e != hipSuccess) return nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+  FitArgs a{};
+  a.P = const_cast<float*>(params);
+  a.samples = (const float4*)samples;
+  a.n = n;
+  a.grad = grad;
+  a.loss = loss;
+  a.n_obj = h->n_obj;
+  hipLaunchKernelGGL(nsdf_fit_kernel<0>, dim3(h->n_obj), dim3(NT), LDS_FIT, (hipStream_t)stream, a);
+  e = hipGetLastError();
+  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+}
+
+tg_status tg_nsdf_adam(float* params, float* m, float* v, const float* grad, int64_t count, int64_t t,
+                       const tg_nsdf_train_params* hp, void* stream) {
+  if (!params || !m || !v || !grad || !hp || count < 1 || t < 1) return TG_ERR_INVALID_ARGUMENT;
+  const float c1 = (float)(1.0 - std::pow((double)hp->beta1, (double)t));
+  const float c2 = (float)(1.0 - std::pow((double)hp->beta2, (double)t));
+  hipLaunchKernelGGL(nsdf_adam_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                     params, m, v, grad, count, hp->lr, hp->beta1, hp->beta2, hp->eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? TG_OK : TG_ERR_HIP;
+}
+
+tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const float* samples, int64_t n,
+                        int64_t step0, int32_t n_steps, const tg_nsdf_train_params* hp, float* loss, void* stream) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  if (!params || !m || !v || !samples || !hp) return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: null pointer");
+  if (n < 1 || n > 0xffffffffLL || step0 < 0 || n_steps < 1 || step0 + n_steps > 0xffffffffLL)
+    return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: bad n / step range");
+  if (hp->batch < 64 || hp->batch % 64) return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: batch must be a multiple of 64");
+  if (!aligned16(samples)) return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: samples not 16-byte aligned");
+  hipError_t e = hipFuncSetAttribute((const void*)nsdf_fit_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     LDS_FIT);
+  if (e != hipSuccess) return nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+  FitArgs a{};
+  a.P = params;
+  a.M = m;
+  a.V = v;
+  a.samples = (const float4*)samples;
+  a.n = n;
+  a.loss = loss;
+  a.step0 = step0;
+  a.n_steps = n_steps;
+  a.n_obj = h->n_obj;
+  a.batch = hp->batch;
+  a.lr = hp->lr;
+  a.b1 = hp->beta1;
+  a.b2 = hp->beta2;
+  a.eps = hp->eps;
+  a.key0 = (uint32_t)hp->seed;
+  a.key1 = (uint32_t)(hp->seed >> 32);
+  hipLaunchKernelGGL(nsdf_fit_kernel<1>, dim3(h->n_obj), dim3(NT), LDS_FIT, (hipStream_t)stream, a);
+  e = hipGetLastError();
+  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+}
+
+tg_status tg_nsdf_query(tg_nsdf* h, const float* params, const int64_t* offsets, int64_t max_count,
+                        const float* xhat, float* out, float* grad, void* stream) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  if (!params || !offsets || !out || !xhat) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query: null pointer");
+  if (max_count < 0) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query: max_count < 0");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(nsdf_pack_kernel, dim3((IMG_WORDS + 255) / 256, h->n_obj), dim3(256), 0, s, params, h->n_obj,
+                     h->d_img);
+  if (max_count > 0) {
+    const int64_t per_block = 4 * 16 * QUERY_TILES_PER_WAVE;
+    const dim3 grid((unsigned)((max_count + per_block - 1) / per_block), (unsigned)h->n_obj);
+    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES, s, h->d_img, offsets, xhat, out, grad);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+}
+
+}  // extern "C"

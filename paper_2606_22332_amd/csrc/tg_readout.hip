@@ -12,6 +12,8 @@
 
 #include "../../include/tg_readout.h"
 #include "link_kernel.h"
+#include "neural_kernel.h"
+#include "nsdf_host.h"
 
 using namespace tg;
 
@@ -66,6 +68,12 @@ struct tg_readout {
   unsigned long long dead_thr = 0;
   size_t state_bytes = 0;
   XtDense xtd;
+  // neural SDF backend (sdf_mode 1)
+  int neural = 0;
+  NBox* d_boxes = nullptr;
+  uint32_t* d_img = nullptr;
+  int32_t* d_order = nullptr;
+  size_t neural_lds = 0;
 };
 
 namespace {
@@ -253,6 +261,13 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
   }
   const uint32_t om = cfg->output_mask;
   if ((om & TG_OUT_NOISY) && !noise) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "noisy outputs need noise");
+  if (cfg->sdf_mode != 0 && cfg->sdf_mode != 1) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "sdf_mode must be 0 or 1");
+  if (cfg->sdf_mode == 1) {
+    if (noise) return fail(nullptr, TG_ERR_UNSUPPORTED, "the neural SDF backend computes the clean readout only");
+    if (!cfg->nsdf_params) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "sdf_mode 1 needs nsdf_params");
+    if (!(cfg->nsdf_band >= 0.f)) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "nsdf_band must be >= 0");
+    if (neural_lds_bytes(L) > 160 * 1024) return fail(nullptr, TG_ERR_UNSUPPORTED, "too many links for the neural kernel");
+  }
 
   tg_readout* h = new (std::nothrow) tg_readout();
   if (!h) return fail(nullptr, TG_ERR_OUT_OF_MEMORY, "host allocation");
@@ -415,6 +430,34 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     tg_readout_destroy(h);
     return fail(nullptr, TG_ERR_HIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
   }
+  if (cfg->sdf_mode == 1) {
+    h->neural = 1;
+    std::vector<NBox> bx(NO);
+    for (int g = 0; g < NO; ++g) {
+      const tg_sdf_grid& G = cfg->grids[g];
+      const float ext = (float)(G.n - 1) * G.spacing;
+      volatile float one = 1.0f;
+      bx[g].half = 0.5f * ext;
+      bx[g].half_inv = one / bx[g].half;
+      for (int i = 0; i < 3; ++i) {
+        bx[g].centre[i] = G.origin[i] + bx[g].half;
+        bx[g].pad[i] = 0.f;
+      }
+    }
+    e = dalloc(h, &h->d_boxes, NO);
+    if (e == hipSuccess) e = dalloc(h, &h->d_img, (size_t)NO * nsdf::IMG_WORDS);
+    if (e == hipSuccess) e = dalloc(h, &h->d_order, E);
+    if (e == hipSuccess) e = hipMemcpy(h->d_boxes, bx.data(), NO * sizeof(NBox), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = nsdf_pack_images(cfg->nsdf_params, NO, h->d_img, nullptr);
+    h->neural_lds = (size_t)neural_lds_bytes(L);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)tg_neural_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)h->neural_lds);
+    if (e != hipSuccess) {
+      tg_readout_destroy(h);
+      return fail(nullptr, TG_ERR_HIP, std::string("neural SDF setup: ") + hipGetErrorString(e));
+    }
+  }
   tg_status st = tg_readout_reset(h, nullptr, 0, nullptr);
   if (st == TG_OK) {
     e = hipDeviceSynchronize();
@@ -473,6 +516,37 @@ tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_s
     return fail(h, TG_ERR_INVALID_ARGUMENT, "link_sums_noisy must be set iff LINK_SUMS and NOISY are requested");
   if (out->link_sums_noisy && !aligned(out->link_sums_noisy, 16))
     return fail(h, TG_ERR_INVALID_ARGUMENT, "link_sums_noisy misaligned");
+
+  if (h->neural) {
+    const int64_t EL = (int64_t)h->E * h->L, ET = (int64_t)h->E * h->T;
+    hipStream_t st = (hipStream_t)hip_stream;
+    for (int s = 0; s < n_steps; ++s) {
+      hipLaunchKernelGGL(tg_group_kernel, dim3(1), dim3(1024), (h->n_obj + 2) * sizeof(int32_t), st,
+                         in->obj_id + (int64_t)s * h->E, h->E, h->n_obj, h->d_order);
+      NLaunch q{};
+      q.kc = h->d_kp;
+      q.boxes = h->d_boxes;
+      q.images = h->d_img;
+      q.order = h->d_order;
+      q.band = h->cfg.nsdf_band;
+      q.step = in->step + s;
+      q.link_state = in->link_state + (int64_t)s * 13 * EL;
+      q.obj_state = in->obj_state ? in->obj_state + (int64_t)s * 13 * h->E : nullptr;
+      q.obj_id = in->obj_id + (int64_t)s * h->E;
+      q.bits = out->contact_bits ? (unsigned long long*)out->contact_bits + (int64_t)s * h->E * h->W : nullptr;
+      q.depth = out->depth ? out->depth + s * ET : nullptr;
+      q.prox = out->prox ? out->prox + s * ET : nullptr;
+      q.surfdist = out->surfdist ? out->surfdist + s * ET : nullptr;
+      q.ft = out->ft ? out->ft + s * 6 * ET : nullptr;
+      q.normal = out->normal ? out->normal + s * 3 * ET : nullptr;
+      q.link_sums = out->link_sums ? out->link_sums + s * 11 * EL : nullptr;
+      hipLaunchKernelGGL(tg_neural_kernel, dim3((h->E + NEU_ENVS - 1) / NEU_ENVS), dim3(NEU_THREADS), h->neural_lds,
+                         st, q);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(h, TG_ERR_HIP, std::string("neural readout launch: ") + hipGetErrorString(e));
+    return TG_OK;
+  }
 
   KLaunch k{};
   k.kc = h->d_kp;

@@ -438,3 +438,85 @@ def subset_envs(inp: Inputs, envs: np.ndarray, L: int) -> Inputs:
     oid = np.ascontiguousarray(inp.obj_id[:, envs])
     os_ = None if inp.obj_state is None else np.ascontiguousarray(inp.obj_state[:, :, envs])
     return Inputs(ls, oid, os_, inp.step0)
+
+
+# ----------------------------------------------------------------------------------------------
+# neural-SDF training inputs: random initial weights and sample points (targets are computed
+# from the grids by the library / the oracle)
+# ----------------------------------------------------------------------------------------------
+NSDF_NUM_PARAMS = 15681
+NSDF_FAN_INS = (48, 64, 64, 64)      # the four hidden layers; the output layer has fan-in 64
+
+
+def nsdf_init(n_obj: int, seed: int) -> np.ndarray:
+    """He-uniform weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)), zero biases: float32 [n_obj, 15681]
+    in the flat order W1[64][48], b1, W2[64][64], b2, W3, b3, W4, b4, w5[64], b5."""
+    rng = np.random.default_rng(seed)
+    P = np.zeros((n_obj, NSDF_NUM_PARAMS), dtype=np.float64)
+    o = 0
+    for fan_in in NSDF_FAN_INS:
+        lim = np.sqrt(6.0 / fan_in)
+        P[:, o:o + 64 * fan_in] = rng.uniform(-lim, lim, (n_obj, 64 * fan_in))
+        o += 64 * fan_in + 64
+    P[:, o:o + 64] = rng.uniform(-np.sqrt(6.0 / 64), np.sqrt(6.0 / 64), (n_obj, 64))
+    return P.astype(np.float32)
+
+
+def _surface_points(s: dict, n: int, rng: np.random.Generator) -> np.ndarray:
+    """n area-uniform points on the surface of analytic shape s (object frame, FP64)."""
+    f = s["family"]
+    if f == "sphere":
+        return random_unit(rng, n) * s["r"]
+    if f == "box":
+        b = s["b"]
+        areas = np.array([b[1] * b[2], b[1] * b[2], b[0] * b[2], b[0] * b[2], b[0] * b[1], b[0] * b[1]])
+        face = rng.choice(6, size=n, p=areas / areas.sum())
+        p = rng.uniform(-1, 1, (n, 3)) * b
+        ax = face // 2
+        p[np.arange(n), ax] = np.where(face % 2 == 0, -1.0, 1.0) * b[ax]
+        return p
+    if f == "capsule":
+        r, hl = s["r"], s["hl"]
+        a_cyl, a_cap = 2 * np.pi * r * 2 * hl, 4 * np.pi * r * r
+        cyl = rng.uniform(size=n) < a_cyl / (a_cyl + a_cap)
+        th = rng.uniform(0, 2 * np.pi, n)
+        p = np.stack([r * np.cos(th), r * np.sin(th), rng.uniform(-hl, hl, n)], axis=1)
+        d = random_unit(rng, n) * r
+        d[:, 2] += np.where(d[:, 2] >= 0, hl, -hl)
+        return np.where(cyl[:, None], p, d)
+    if f == "torus":
+        R, r = s["R"], s["r"]
+        out = np.empty((0, 3))
+        while out.shape[0] < n:
+            m = 2 * (n - out.shape[0]) + 16
+            u, v = rng.uniform(0, 2 * np.pi, m), rng.uniform(0, 2 * np.pi, m)
+            keep = rng.uniform(size=m) < (R + r * np.cos(v)) / (R + r)
+            u, v = u[keep], v[keep]
+            rho = R + r * np.cos(v)
+            out = np.concatenate([out, np.stack([rho * np.cos(u), rho * np.sin(u), r * np.sin(v)], axis=1)])
+        return out[:n]
+    if f == "hull":
+        v, t = s["verts"], s["tris"]
+        a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+        area = 0.5 * np.linalg.norm(np.cross(b - a, c - a), axis=1)
+        k = rng.choice(t.shape[0], size=n, p=area / area.sum())
+        u1, u2 = rng.uniform(size=n), rng.uniform(size=n)
+        su = np.sqrt(u1)
+        return (1 - su)[:, None] * a[k] + (su * (1 - u2))[:, None] * b[k] + (su * u2)[:, None] * c[k]
+    raise ValueError(f)
+
+
+def nsdf_points(grids: List[Grid], n: int, seed: int, sigma: float = 2e-3) -> np.ndarray:
+    """Training points float32 [n_obj, n, 3] (object frame): the first n//2 are area-uniform surface
+    points of the analytic shape plus an isotropic N(0, sigma^2) offset, the rest are uniform in
+    the grid box.  Points are clamped into the box."""
+    rng = np.random.default_rng(seed)
+    out = np.empty((len(grids), n, 3), dtype=np.float32)
+    for o, g in enumerate(grids):
+        lo = g.origin.astype(np.float64)
+        hi = lo + (g.n - 1) * float(g.spacing)
+        ns = n // 2
+        near = _surface_points(g.shape, ns, rng) + rng.normal(0.0, sigma, (ns, 3))
+        uni = rng.uniform(lo, hi, (n - ns, 3))
+        out[o] = np.clip(np.concatenate([near, uni]), lo, hi)
+    return out

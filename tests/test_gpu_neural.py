@@ -1,0 +1,140 @@
+"""Readout with the neural SDF backend (sdf_mode 1) against the CPU oracle, through the C ABI.
+
+- band larger than any |phi|: every probe takes the grid fallback, so the result must meet the
+  grid path's bar (masks and depth bit-exact, F/T within 1e-5) against the grid oracle;
+- band 0: every probe inside an object's box takes the network; compared with the oracle's
+  neural backend (BF16-emulating network in FP64), held to the network's own tolerance: phi
+  within 20 um, normals within 0.1 deg, and the downstream outputs within what those allow;
+- band 1 mm: each probe must equal either the grid value (bitwise) or the network value, and
+  the choice must follow |phi_nn| < band wherever that is decided beyond the 20 um tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import parity
+from paper_2606_22332_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+CLEAN_MASK = 1 | 2 | 4 | 8 | 32 | 64 | 128     # bits, depth, prox, ft, normal, surfdist, link sums
+
+
+def clean_scene(E=48, S=3, cfg="c2"):
+    sc = synth.make_scene(cfg, num_envs=E, num_steps=S)
+    sc.noise = synth.NoiseParams(enabled=False, seed=sc.noise.seed)
+    return sc
+
+
+def params_for(sc, seed=5, bias_sigma=0.05):
+    P = synth.nsdf_init(len(sc.grids), seed).astype(np.float64)
+    rng = np.random.default_rng(seed)
+    P[:, 15680] = rng.normal(0.0, bias_sigma, len(sc.grids))
+    return P.astype(np.float32)
+
+
+def run_neural(sc, inp, P, band, mask=CLEAN_MASK):
+    import torch
+    from paper_2606_22332_amd import binding as B
+    dP = torch.from_numpy(P).cuda()
+    ro = B.Readout(sc, mask, nsdf_params=dP, nsdf_band=band)
+    S = inp.link_state.shape[0]
+    ro.alloc_outputs(S)
+    ro.rollout(B.to_device(inp), S)
+    torch.cuda.synchronize()
+    res = {k: v.cpu().numpy() for k, v in ro.out.items()}
+    ro.out = {}
+    ro.close()
+    return res
+
+
+def with_edge_envs(inp, E):
+    oid = inp.obj_id.copy()
+    oid[:, 3] = -1                      # no object
+    oid[:, 7] = 10_000                  # out of range: treated as no object
+    inp.obj_id = oid
+    return inp
+
+
+@pytest.mark.parametrize("moving", [False, True])
+def test_band_everywhere_equals_grid_path(torch_cuda, moving):
+    sc = clean_scene()
+    inp = with_edge_envs(synth.make_inputs(sc), sc.num_envs)
+    if moving:
+        inp.obj_state = synth.random_object_state(sc, inp.link_state.shape[0])
+    P = params_for(sc)
+    g = run_neural(sc, inp, P, band=1e9)
+    ref = oracle.run_readout(sc, inp, precision="f32")
+    parity.compare(g, ref, sc.layout.num_taxels, noisy=False, link_offset=sc.layout.link_offset)
+
+
+def neural_tolerances(g, r, k_n, taxel_pos):
+    """Downstream bars from 20 um on phi and 0.1 deg on the normal."""
+    dphi = 20e-6
+    act = r["surfdist"] < 1e30
+    assert np.all(np.abs(g["surfdist"][act] - r["surfdist"][act]) <= dphi)
+    assert np.all(np.abs(g["depth"] - r["depth"]) <= dphi)
+    assert np.all(np.abs(g["prox"] - r["prox"]) <= 150.0 * dphi + 1e-6)
+    bits_g = parity.unpack_bits(g["bits"], g["depth"].shape[-1]).astype(bool)
+    decided = np.abs(r["depth"] - 5e-4) > dphi
+    assert np.array_equal(bits_g[decided], r["bit"].astype(bool)[decided])
+    both = (g["depth"] > 0) & (r["depth"] > 0)
+    ng = np.moveaxis(g["normal"], 1, -1)[both]
+    nr = np.moveaxis(r["normal"], 1, -1)[both]
+    cosang = np.clip(np.sum(ng * nr, -1) / np.maximum(np.linalg.norm(ng, axis=-1) * np.linalg.norm(nr, axis=-1),
+                                                       1e-30), -1, 1)
+    ang = np.degrees(np.arccos(cosang))
+    if ang.size:
+        assert np.quantile(ang, 0.999) <= 0.1 and ang.max() <= 1.0, (np.quantile(ang, 0.999), ang.max())
+    gf, gt = parity.ft_vectors(g["ft"].astype(np.float64))
+    rf, rt = parity.ft_vectors(r["ft"])
+    xmax = float(np.abs(taxel_pos).max()) + 0.05
+    tol_f = k_n * 1.5 * dphi + 3e-3 * np.abs(rf).max(-1)
+    tol_t = xmax * k_n * 1.5 * dphi + 3e-3 * np.maximum(np.abs(rt).max(-1), xmax * np.abs(rf).max(-1))
+    assert np.all(np.abs(gf - rf).max(-1) <= tol_f)
+    assert np.all(np.abs(gt - rt).max(-1) <= tol_t)
+    return dict(max_dphi_um=float(np.abs(g["surfdist"][act] - r["surfdist"][act]).max() * 1e6),
+                contacts=int(both.sum()), max_angle=float(ang.max() if ang.size else 0.0))
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_network_everywhere_matches_neural_oracle(torch_cuda, cfg):
+    sc = clean_scene(E=40 if cfg == "c2" else 12, S=2, cfg=cfg)
+    inp = with_edge_envs(synth.make_inputs(sc), sc.num_envs)
+    P = params_for(sc, seed=7)
+    g = run_neural(sc, inp, P, band=0.0)
+    r = oracle.run_readout(sc, inp, precision="f32", nsdf_params=P, nsdf_band=0.0)
+    info = neural_tolerances(g, r, sc.force.k_n, sc.layout.pos)
+    assert info["contacts"] > 0
+    print(info)
+
+
+def test_band_switches_between_grid_and_network(torch_cuda):
+    sc = clean_scene(E=40, S=2)
+    inp = synth.make_inputs(sc)
+    P = params_for(sc, seed=9, bias_sigma=0.002)
+    band = 1e-3
+    g = run_neural(sc, inp, P, band=band)
+    r_grid = oracle.run_readout(sc, inp, precision="f32")
+    r_nn = oracle.run_readout(sc, inp, precision="f32", nsdf_params=P, nsdf_band=0.0)
+    s_g, s_grid, s_nn = g["surfdist"].astype(np.float64), r_grid["surfdist"], r_nn["surfdist"]
+    act = s_grid < 1e30
+    boxed = act & (s_nn != s_grid)          # inside the box: the band-0 oracle used the network
+    far = act & ~boxed                      # outside the box both oracles keep the grid value
+    inb = boxed & (np.abs(s_nn) < band - 25e-6)
+    out = boxed & (np.abs(s_nn) > band + 25e-6)
+    amb = boxed & ~inb & ~out
+    assert np.array_equal(s_g[far], s_grid[far])
+    assert np.array_equal(s_g[inb], s_grid[inb])
+    assert np.all(np.abs(s_g[out] - s_nn[out]) <= 20e-6)
+    assert np.all((s_g[amb] == s_grid[amb]) | (np.abs(s_g[amb] - s_nn[amb]) <= 20e-6))
+    assert inb.sum() > 0 and out.sum() > 0

@@ -1,0 +1,227 @@
+"""Neural-SDF kernels (include/tg_nsdf.h) against the CPU oracle, through the C ABI.
+
+Inputs: seeded He-uniform weights and sample points from the scene generator; training
+records (x_hat, phi/e) come from the oracle's FP64 grid interpolation, never from the GPU.
+Bars: training targets within FP32 rounding of the FP64 records; network output within 20 um
+(phi = e * out) of the BF16-emulating oracle and its input gradient within 0.1 deg; the loss
+gradient within 1e-2 (norm-wise per layer) of FP64 backprop and tighter against the
+BF16-emulating backprop; Adam within FP32 rounding of the FP64 update.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2606_22332_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+NP = 15681
+LAYERS = {"W1": (0, 3072), "b1": (3072, 3136), "W2": (3136, 7232), "b2": (7232, 7296), "W3": (7296, 11392),
+          "b3": (11392, 11456), "W4": (11456, 15552), "b4": (15552, 15616), "w5": (15616, 15680),
+          "b5": (15680, 15681)}
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def grids():
+    return synth.make_scene("c2", num_envs=4, num_steps=2).grids
+
+
+def half_extent(g):
+    return 0.5 * (g.n - 1) * float(g.spacing)
+
+
+def init_params(n_obj, seed, bias_sigma=0.1):
+    P = synth.nsdf_init(n_obj, seed).astype(np.float64)
+    rng = np.random.default_rng(seed + 1)
+    for name in ("b1", "b2", "b3", "b4", "b5"):
+        a, b = LAYERS[name]
+        P[:, a:b] = rng.normal(0, bias_sigma, (n_obj, b - a))
+    return P.astype(np.float32)
+
+
+def records(grids, n, seed):
+    pts = synth.nsdf_points(grids, n, seed)
+    return np.stack([oracle.nsdf_targets(g, p) for g, p in zip(grids, pts)]).astype(np.float32)
+
+
+def test_targets_match_oracle(torch_cuda, grids):
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    n = 1000
+    pts = synth.nsdf_points(grids, n, 11)
+    rng = np.random.default_rng(12)
+    for o, g in enumerate(grids):            # some points outside the box exercise the clamp
+        lo = g.origin.astype(np.float64); hi = lo + (g.n - 1) * float(g.spacing)
+        pts[o, :40] = rng.uniform(lo - 0.01, hi + 0.01, (40, 3))
+    ns = B.Nsdf(grids)
+    rec = ns.targets(torch.from_numpy(pts).cuda()).cpu().numpy()
+    ns.close()
+    for o, g in enumerate(grids):
+        ref = oracle.nsdf_targets(g, pts[o])
+        np.testing.assert_allclose(rec[o, :, :3], ref[:, :3], atol=2e-6, rtol=0)
+        np.testing.assert_allclose(rec[o, :, 3], ref[:, 3], atol=1e-6, rtol=0)
+        assert np.all(np.abs(rec[o, :, :3]) <= 1.0)
+
+
+@pytest.mark.parametrize("counts", [[1, 37, 300], [0, 64, 129]])
+def test_query_matches_bf16_oracle(torch_cuda, grids, counts):
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    gs = grids[:len(counts)]
+    P = init_params(len(gs), 21)
+    rng = np.random.default_rng(22)
+    xs = [rng.uniform(-1, 1, (c, 3)).astype(np.float32) for c in counts]
+    if counts[-1] >= 8:
+        xs[-1][:8] = np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1) for sz in (-1, 1)], np.float32)
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    X = np.concatenate(xs)
+    ns = B.Nsdf(gs)
+    dP = torch.from_numpy(P).cuda()
+    out, gx = ns.query(dP, offs, torch.from_numpy(X).cuda(), grad=True)
+    out2 = ns.query(dP, offs, torch.from_numpy(X).cuda(), grad=False)
+    torch.cuda.synchronize()
+    out, gx, out2 = out.cpu().numpy(), gx.cpu().numpy(), out2.cpu().numpy()
+    ns.close()
+    assert np.array_equal(out, out2)
+    for o, g in enumerate(gs):
+        sl = slice(offs[o], offs[o + 1])
+        if counts[o] == 0:
+            continue
+        ref, rg = oracle.nsdf_forward(P[o].astype(np.float64), X[sl].astype(np.float64), grad=True, bf16=True)
+        e = half_extent(g)
+        err_um = np.abs(out[sl] - ref) * e * 1e6
+        assert err_um.max() <= 20.0, (o, err_um.max())
+        nr = np.linalg.norm(rg, axis=1)
+        ng = np.linalg.norm(gx[sl], axis=1)
+        cosang = np.sum(rg * gx[sl], axis=1) / np.maximum(nr * ng, 1e-30)
+        ang = np.degrees(np.arccos(np.clip(cosang, -1, 1)))
+        ok = nr > 1e-3 * np.median(nr)
+        assert ang[ok].max() <= 0.1, (o, ang[ok].max())
+        assert np.all(np.abs(ng - nr) <= 1e-2 * nr + 1e-6)
+
+
+def layer_rel(a, b):
+    return {k: np.linalg.norm(a[s:e] - b[s:e]) / max(np.linalg.norm(b[s:e]), 1e-30) for k, (s, e) in LAYERS.items()}
+
+
+def test_grad_matches_oracle(torch_cuda, grids):
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    gs = grids[:3]
+    n = 200                                   # 12.5 tiles of 16: ragged tail
+    P = init_params(len(gs), 31)
+    S = records(gs, n, 32)
+    ns = B.Nsdf(gs)
+    loss, G = ns.grad(torch.from_numpy(P).cuda(), torch.from_numpy(S).cuda())
+    torch.cuda.synchronize()
+    loss, G = loss.cpu().numpy(), G.cpu().numpy()
+    ns.close()
+    for o in range(len(gs)):
+        x, t = S[o, :, :3].astype(np.float64), S[o, :, 3].astype(np.float64)
+        l64, g64 = oracle.nsdf_loss_grad(P[o].astype(np.float64), x, t)
+        lbf, gbf = oracle.nsdf_loss_grad(P[o].astype(np.float64), x, t, bf16=True)
+        assert abs(loss[o] - lbf) <= 1e-5 * abs(lbf)
+        r64 = layer_rel(G[o].astype(np.float64), g64)
+        rbf = layer_rel(G[o].astype(np.float64), gbf)
+        assert max(r64.values()) <= 1e-2, r64
+        assert max(rbf.values()) <= 2e-3, rbf
+
+
+def test_adam_matches_oracle(torch_cuda):
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    rng = np.random.default_rng(41)
+    n = 2 * NP + 7
+    P = rng.normal(0, 0.3, n).astype(np.float32)
+    m = rng.normal(0, 1e-3, n).astype(np.float32)
+    v = rng.uniform(0, 1e-5, n).astype(np.float32)
+    g = rng.normal(0, 1e-2, n).astype(np.float32)
+    hp = B.train_params(lr=1e-3)
+    ns = B.Nsdf(synth.make_scene("c1", num_envs=1, num_steps=1).grids)
+    dP, dm, dv, dg = (torch.from_numpy(a).cuda() for a in (P, m, v, g))
+    ns.adam(dP, dm, dv, dg, 7, hp)
+    torch.cuda.synchronize()
+    ns.close()
+    P64, m64, v64 = P.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    oracle.nsdf_adam(P64, m64, v64, g.astype(np.float64), 7, lr=1e-3)
+    np.testing.assert_allclose(dP.cpu().numpy(), P64, rtol=1e-6, atol=1e-8)
+    np.testing.assert_allclose(dm.cpu().numpy(), m64, rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(dv.cpu().numpy(), v64, rtol=1e-6, atol=1e-14)
+
+
+def minibatch_indices(o, step, batch, n, seed):
+    """Record indices of one object's minibatch: Philox4x32-10 with key (seed lo, seed hi) and
+    counter (object, step, j / 4, 8), word j % 4, index = (word * n) >> 32 (oracle's generator)."""
+    key = [seed & 0xffffffff, seed >> 32]
+    idx = np.empty(batch, np.int64)
+    for q in range(batch // 4):
+        w = oracle.philox4x32_10([o, step, q, 8], key)
+        idx[4 * q:4 * q + 4] = (w.astype(np.uint64) * np.uint64(n)) >> np.uint64(32)
+    return idx
+
+
+def test_fused_training_equals_grad_then_adam(torch_cuda, grids):
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    gs = grids[:2]
+    n, batch, steps, seed = 3000, 128, 3, 0x1234_0000_0042
+    P0 = init_params(len(gs), 51)
+    S = records(gs, n, 52)
+    hp = B.train_params(lr=1e-3, batch=batch, seed=seed)
+    ns = B.Nsdf(gs)
+    dS = torch.from_numpy(S).cuda()
+    Pf = torch.from_numpy(P0).cuda(); mf = torch.zeros_like(Pf); vf = torch.zeros_like(Pf)
+    lf = torch.zeros((steps, len(gs)), device="cuda")
+    ns.train(Pf, mf, vf, dS, 0, steps, hp, loss=lf)
+    Pc = torch.from_numpy(P0).cuda(); mc = torch.zeros_like(Pc); vc = torch.zeros_like(Pc)
+    lc = []
+    for t in range(1, steps + 1):
+        idx = np.stack([minibatch_indices(o, t, batch, n, seed) for o in range(len(gs))])
+        sub = torch.stack([dS[o, torch.from_numpy(idx[o]).cuda()] for o in range(len(gs))]).contiguous()
+        loss, G = ns.grad(Pc, sub)
+        ns.adam(Pc, mc, vc, G, t, hp)
+        lc.append(loss.cpu().numpy())
+    torch.cuda.synchronize()
+    ns.close()
+    np.testing.assert_allclose(lf.cpu().numpy(), np.stack(lc), rtol=1e-5)
+    dPf, dPc = (Pf.cpu().numpy() - P0), (Pc.cpu().numpy() - P0)
+    for o in range(len(gs)):
+        assert np.linalg.norm(dPf[o] - dPc[o]) <= 1e-3 * np.linalg.norm(dPc[o])
+
+
+def test_training_fits_a_sphere(torch_cuda):
+    """Fused GPU training on the sphere grid cuts the L1 loss several-fold in 400 steps and the
+    trained network's surface error falls well below the initial one."""
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    gs = synth.make_scene("c1", num_envs=1, num_steps=1).grids
+    n = 1 << 15
+    S = records(gs, n, 61)
+    P0 = synth.nsdf_init(1, 62)
+    hp = B.train_params(lr=1e-3, batch=1024, seed=63)
+    ns = B.Nsdf(gs)
+    P = torch.from_numpy(P0).cuda(); m = torch.zeros_like(P); v = torch.zeros_like(P)
+    L = torch.zeros((400, 1), device="cuda")
+    ns.train(P, m, v, torch.from_numpy(S).cuda(), 0, 400, hp, loss=L)
+    x = torch.from_numpy(np.ascontiguousarray(S[0, :2000, :3])).cuda()
+    out0 = ns.query(torch.from_numpy(P0).cuda(), [0, 2000], x, grad=False)
+    out1 = ns.query(P, [0, 2000], x, grad=False)
+    torch.cuda.synchronize()
+    ns.close()
+    L = L.cpu().numpy()[:, 0]
+    assert L[-20:].mean() < 0.2 * L[:5].mean(), (L[:5], L[-20:])
+    e = half_extent(gs[0])
+    err0 = np.abs(out0.cpu().numpy() - S[0, :2000, 3]) * e
+    err1 = np.abs(out1.cpu().numpy() - S[0, :2000, 3]) * e
+    assert math.isfinite(float(np.median(err1)))
+    assert np.median(err1) < 0.2 * np.median(err0), (np.median(err0), np.median(err1))

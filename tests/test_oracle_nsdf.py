@@ -133,3 +133,50 @@ def test_small_fit_converges_on_a_sphere():
         oracle.nsdf_adam(P, m, v, g, t, lr=1e-3)
         losses.append(loss)
     assert np.mean(losses[-20:]) < 0.25 * np.mean(losses[:5])
+
+
+def test_bf16_loss_gradient_tracks_fp64():
+    """The BF16-emulating backprop stays within a few BF16 ulps of exact backprop, layer by layer."""
+    rng = np.random.default_rng(7)
+    P = he_init(rng)
+    x = rng.uniform(-1, 1, (64, 3))
+    t = rng.normal(0, 0.3, 64)
+    l64, g64 = oracle.nsdf_loss_grad(P, x, t)
+    lbf, gbf = oracle.nsdf_loss_grad(P, x, t, bf16=True)
+    assert abs(lbf - l64) < 0.02 * l64
+    for (a, b) in offsets()[:4]:
+        w = slice(a, b)
+        assert np.linalg.norm(gbf[w] - g64[w]) < 2e-2 * np.linalg.norm(g64[w])
+
+
+def test_targets_reproduce_a_plane_and_clamp_to_the_box():
+    """Trilinear interpolation reproduces a linear field exactly (up to rounding of the FP32 grid);
+    points outside the box are clamped onto it before the lookup."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    import helpers
+    nrm = np.array([0.3, -0.5, 0.8]); nrm /= np.linalg.norm(nrm)
+    g = helpers.plane_grid(normal=nrm, offset=0.004, n=16, side=0.08)
+    rng = np.random.default_rng(8)
+    pts = rng.uniform(-0.06, 0.06, (500, 3)).astype(np.float32)
+    rec = oracle.nsdf_targets(g, pts)
+    lo = g.origin.astype(np.float64); hi = lo + 15 * float(g.spacing)
+    q = np.clip(pts.astype(np.float64), lo, hi)
+    e = 0.5 * 15 * float(g.spacing)
+    np.testing.assert_allclose(rec[:, :3], (q - (lo + e)) / e, atol=1e-14)
+    np.testing.assert_allclose(rec[:, 3] * e, q @ nrm - 0.004, atol=2e-8)
+    assert np.all(np.abs(rec[:, :3]) <= 1 + 1e-12)
+
+
+def test_generated_surface_points_lie_on_the_shapes():
+    from paper_2606_22332_amd import synth
+    grids = synth.make_scene("c2", num_envs=2, num_steps=1).grids
+    rng = np.random.default_rng(9)
+    for g in grids:
+        p = synth._surface_points(g.shape, 500, rng)
+        assert np.abs(synth.shape_sdf(g.shape, p)).max() < 1e-12, g.family
+    P = synth.nsdf_init(3, 10)
+    assert P.shape == (3, NP) and P.dtype == np.float32
+    W1 = P[:, :F * H]
+    assert abs(W1.std() - math.sqrt(6 / F) / math.sqrt(3)) < 0.01
+    assert np.all(P[:, F * H:F * H + H] == 0)
