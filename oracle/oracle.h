@@ -83,9 +83,35 @@ typedef struct {
   double* gain;                /* [E][T] */
 } or_state;
 
+/* Thermal fields (App. D, thermal sensing; explicit voxel solver): one n^3 field per env on each
+ * listed link, in that link's frame.  Temperatures in degC. */
+typedef struct {
+  int32_t num_fields;          /* fields per env */
+  const int32_t* field_link;   /* [num_fields] link of each field */
+  int32_t n;                   /* voxels per axis */
+  float dx;                    /* voxel edge [m] */
+  float origin[3];             /* link-frame position of the outer corner of voxel (0,0,0) */
+  float dt;                    /* [s] */
+  float k_sensor, rho_cp, emissivity, k_object, d_w;
+  float T0, T_amb;             /* initial and ambient temperature */
+  float P_gen;                 /* uniform internal generation per field [W] */
+  const float* T_obj;          /* [E] object temperature per env */
+} or_thermal;
+
+typedef struct {               /* derived constants, FP64 */
+  double alpha, r, h_r, rho_f, g, k_eff, kappa;
+} or_thermal_consts;
+
 #ifdef __cplusplus
 extern "C" {
 #endif
+void or_thermal_constants(const or_thermal* th, or_thermal_consts* K);
+int or_thermal_voxel(const or_thermal* th, const float* x);
+int or_thermal_stable(const or_thermal* th, double delta_max, int32_t taxels_per_voxel_max);
+int or_thermal_run_f32(const or_thermal* th, int32_t E, int32_t T, const int32_t* link_offset, const float* taxel_pos,
+                       const double* depth, int32_t S, float* fields, double* taxel_temp, double* ledger);
+int or_thermal_run_f64(const or_thermal* th, int32_t E, int32_t T, const int32_t* link_offset, const float* taxel_pos,
+                       const double* depth, int32_t S, double* fields, double* taxel_temp, double* ledger);
 void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 int or_reset_f32(const or_problem* P, or_state* st, const uint8_t* env_mask, int64_t reset_step);
 int or_reset_f64(const or_problem* P, or_state* st, const uint8_t* env_mask, int64_t reset_step);

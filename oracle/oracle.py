@@ -276,3 +276,92 @@ def nsdf_targets(grid, points):
     lib.or_nsdf_targets(int(grid.n), org.ctypes.data, float(grid.spacing), vals.ctypes.data,
                         pts.shape[0], pts.ctypes.data, rec.ctypes.data)
     return rec
+
+
+# ------------------------------------------------------------------------------------------------
+# thermal fields (thermal.c)
+# ------------------------------------------------------------------------------------------------
+class OrThermal(C.Structure):
+    _fields_ = [("num_fields", C.c_int32), ("field_link", C.c_void_p), ("n", C.c_int32), ("dx", C.c_float),
+                ("origin", C.c_float * 3), ("dt", C.c_float), ("k_sensor", C.c_float), ("rho_cp", C.c_float),
+                ("emissivity", C.c_float), ("k_object", C.c_float), ("d_w", C.c_float), ("T0", C.c_float),
+                ("T_amb", C.c_float), ("P_gen", C.c_float), ("T_obj", C.c_void_p)]
+
+
+class OrThermalConsts(C.Structure):
+    _fields_ = [(k, C.c_double) for k in ("alpha", "r", "h_r", "rho_f", "g", "k_eff", "kappa")]
+
+
+def _thermal_lib():
+    lib = _load()
+    if not getattr(lib, "_th_ready", False):
+        lib.or_thermal_constants.argtypes = [C.c_void_p, C.c_void_p]
+        lib.or_thermal_voxel.argtypes = [C.c_void_p, C.c_void_p]
+        lib.or_thermal_voxel.restype = C.c_int
+        lib.or_thermal_stable.argtypes = [C.c_void_p, C.c_double, C.c_int32]
+        lib.or_thermal_stable.restype = C.c_int
+        for nm in ("or_thermal_run_f32", "or_thermal_run_f64"):
+            getattr(lib, nm).argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                         C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+            getattr(lib, nm).restype = C.c_int
+        lib._th_ready = True
+    return lib
+
+
+def _thermal_struct(th, keep):
+    links = np.ascontiguousarray(th.field_links, np.int32)
+    tobj = np.ascontiguousarray(th.T_obj, np.float32)
+    keep += [links, tobj]
+    s = OrThermal()
+    s.num_fields, s.field_link, s.n, s.dx = len(links), links.ctypes.data, th.n, th.dx
+    s.origin[:] = [float(x) for x in th.origin]
+    s.dt, s.k_sensor, s.rho_cp, s.emissivity = th.dt, th.k_sensor, th.rho_cp, th.emissivity
+    s.k_object, s.d_w, s.T0, s.T_amb, s.P_gen = th.k_object, th.d_w, th.T0, th.T_amb, th.P_gen
+    s.T_obj = tobj.ctypes.data
+    return s
+
+
+def thermal_constants(th) -> dict:
+    keep = []
+    s = _thermal_struct(th, keep)
+    K = OrThermalConsts()
+    _thermal_lib().or_thermal_constants(C.byref(s), C.byref(K))
+    return {k: getattr(K, k) for k, _ in K._fields_}
+
+
+def thermal_voxel(th, x) -> int:
+    keep = []
+    s = _thermal_struct(th, keep)
+    xx = np.ascontiguousarray(x, np.float32)
+    return int(_thermal_lib().or_thermal_voxel(C.byref(s), xx.ctypes.data))
+
+
+def thermal_stable(th, delta_max: float, taxels_per_voxel_max: int) -> bool:
+    keep = []
+    s = _thermal_struct(th, keep)
+    return bool(_thermal_lib().or_thermal_stable(C.byref(s), float(delta_max), int(taxels_per_voxel_max)))
+
+
+def thermal_run(th, layout, depth, fields=None, precision="f64"):
+    """Integrate the fields over the steps of `depth` ([S][E][T] clean depths).  fields: [E][F][n][n][n]
+    initial state (default: T0 everywhere), updated in place.  Returns (fields, taxel_temp [S][E][T],
+    ledger [S][E][F][2] = (stored energy change, source energy) in J)."""
+    lib = _thermal_lib()
+    keep = []
+    s = _thermal_struct(th, keep)
+    depth = np.ascontiguousarray(depth, np.float64)
+    S, E, T = depth.shape
+    F, n = len(th.field_links), th.n
+    dt = np.float32 if precision == "f32" else np.float64
+    if fields is None:
+        fields = np.full((E, F, n, n, n), th.T0, dtype=dt)
+    assert fields.dtype == dt and fields.flags.c_contiguous and fields.shape == (E, F, n, n, n)
+    off = np.ascontiguousarray(layout.link_offset, np.int32)
+    pos = np.ascontiguousarray(layout.pos, np.float32)
+    tt = np.zeros((S, E, T))
+    led = np.zeros((S, E, F, 2))
+    fn = lib.or_thermal_run_f32 if precision == "f32" else lib.or_thermal_run_f64
+    rc = fn(C.byref(s), E, T, off.ctypes.data, pos.ctypes.data, depth.ctypes.data, S, fields.ctypes.data,
+            tt.ctypes.data, led.ctypes.data)
+    assert rc == 0
+    return fields, tt, led

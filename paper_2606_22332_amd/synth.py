@@ -116,6 +116,25 @@ class NoiseParams:
 
 
 @dataclass
+class ThermalParams:
+    """Voxel temperature fields on some links (one n^3 block per env and link, link frame)."""
+    field_links: List[int]
+    T_obj: np.ndarray                     # float32 [E] object temperature per env [degC]
+    n: int = 16
+    dx: float = 1e-3
+    origin: tuple = (-8e-3, -8e-3, -16e-3)   # outer corner of voxel (0,0,0); top face at z = 0
+    dt: float = 1e-3
+    k_sensor: float = 0.2
+    rho_cp: float = 2.0e6
+    emissivity: float = 0.85
+    k_object: float = 10.0
+    d_w: float = 1.0
+    T0: float = 22.0
+    T_amb: float = 22.0
+    P_gen: float = 0.1
+
+
+@dataclass
 class Scene:
     name: str
     num_envs: int
@@ -126,6 +145,7 @@ class Scene:
     noise: NoiseParams
     dt: float = 0.005
     geom_seed: int = MASTER_SEED
+    thermal: Optional[ThermalParams] = None
 
 
 @dataclass
@@ -342,6 +362,9 @@ def make_scene(cfg: str, num_envs: Optional[int] = None, num_steps: Optional[int
         sc.num_envs = num_envs
     if num_steps is not None:
         sc.num_steps = num_steps
+    if cfg == "c5":        # fingertips are links 1..5 of the hand; object temperature U(10, 60) degC
+        trng = np.random.default_rng(MASTER_SEED + 50)
+        sc.thermal = ThermalParams([1, 2, 3, 4, 5], trng.uniform(10.0, 60.0, sc.num_envs).astype(np.float32))
     return sc
 
 
