@@ -59,7 +59,8 @@ enum {
   TG_OUT_NOISY = 1u << 4,      /* ft_noisy + contact_bits_noisy (noise enabled)  */
   TG_OUT_NORMAL = 1u << 5,     /* normal                                         */
   TG_OUT_SURFDIST = 1u << 6,   /* surfdist                                       */
-  TG_OUT_LINK_SUMS = 1u << 7   /* link_sums (+ link_sums_noisy when NOISY)       */
+  TG_OUT_LINK_SUMS = 1u << 7,  /* link_sums (+ link_sums_noisy when NOISY)       */
+  TG_OUT_TEMP = 1u << 8        /* temperature (thermal fields configured)        */
 };
 
 /* One object's signed-distance field sampled on a node-centred cube grid in the object
@@ -100,6 +101,32 @@ typedef struct {
   float eta_off;           /* Schmitt release threshold of the noisy bit (<= eta_on) */
 } tg_noise_desc;
 
+/* Voxel temperature fields (App. D, thermal sensing, with the explicit solver of the
+ * configuration in place of the paper's spectral one): one 16^3 block per env on each listed
+ * link, in that link's frame, voxel edge dx, outer corner of voxel (0,0,0) at `origin`, taxels
+ * over the top layer (z index 15).  Per step and voxel, explicit Euler of
+ *   rho c_p dT/dt = k lap T + generation + contact conduction - linearised radiation
+ * with insulated (mirrored) faces; P_gen spread uniformly over the block; radiation
+ * h_r = 4 eps sigma T_amb^3 on every face of the block; contact conduction into the top-layer
+ * voxel under each taxel at rate dt pi d_w k_eff d_j / (rho c_p dx^3) per kelvin of
+ * (T_obj - T), k_eff = 2 k_sensor k_object / (k_sensor + k_object), d_j the taxel's clean
+ * depth.  create returns TG_ERR_UNSTABLE unless 6 r + 3 rho_f + kappa d_max m <= 1 (r =
+ * alpha dt / dx^2, rho_f = dt h_r / (rho c_p dx), kappa the contact rate per metre of depth,
+ * d_max the largest clean depth the grids allow, m the most taxels over one voxel), which
+ * keeps every update a non-negative combination of old temperatures. */
+typedef struct {
+  int32_t num_fields;            /* thermal links per env (>= 1)                          */
+  const int32_t* field_links;    /* host [num_fields], distinct links                     */
+  int32_t n;                     /* voxels per axis: 16                                   */
+  float dx;                      /* voxel edge [m]                                        */
+  float origin[3];               /* link-frame outer corner of voxel (0,0,0) [m]          */
+  float dt;                      /* step [s]                                              */
+  float k_sensor, rho_cp, emissivity, k_object, d_w;
+  float T0, T_amb;               /* initial (at reset) and ambient temperature [degC]     */
+  float P_gen;                   /* internal generation per block [W]                     */
+  const float* T_obj;            /* host [num_envs] object temperature [degC]; copied     */
+} tg_thermal_desc;
+
 typedef struct {
   uint32_t abi_version;            /* TG_ABI_VERSION */
   int32_t num_envs, num_links, num_taxels, num_objects;
@@ -124,6 +151,7 @@ typedef struct {
   float nsdf_band;                 /* [m], >= 0 (mode 1)                                   */
   const float* nsdf_params;        /* device [num_objects][15681] FP32; read during create
                                       only (packed into library-owned BF16 images)          */
+  const tg_thermal_desc* thermal;  /* NULL = no thermal fields (requires sdf_mode 0)       */
 } tg_readout_config;
 
 /* Per-step inputs, device, SoA.  For tg_readout_rollout each array holds n_steps
@@ -152,6 +180,8 @@ typedef struct {
   float* link_sums;              /* [11][E][L] sum f(3), sum tau(3), count, agg_bool,
                                     agg_force = 1e4 (sum d n_z, sum d n_y, sum d n_x)       */
   float* link_sums_noisy;        /* [11][E][L] same on the noisy channel                   */
+  float* temperature;            /* [E][T] after the step: temperature of the top-layer voxel
+                                    under each taxel of a thermal link, 0 elsewhere         */
 } tg_step_outputs;
 
 /* Create a handle: validates the configuration, deep-copies every host array to device
@@ -173,7 +203,9 @@ tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_s
  * nonzero = reset that env; NULL = all envs.  The draws use counter (env, taxel, step, 7). */
 tg_status tg_readout_reset(tg_readout* h, const uint8_t* env_mask_dev, int64_t step, void* hip_stream);
 
-/* Size in bytes of the noise state (drift, hysteresis, Schmitt, dead, stuck, gain). */
+/* Size in bytes of the dynamic state: noise state (drift, hysteresis, Schmitt, dead, stuck,
+ * gain) followed, with thermal fields, by the fields as float [E][num_fields][16][16][16]
+ * (index ((z * 16) + y) * 16 + x, degC).  Reset sets the fields of the reset envs to T0. */
 tg_status tg_readout_state_size(const tg_readout* h, size_t* bytes);
 /* Copy the noise state to / from a device buffer of tg_readout_state_size bytes (checkpoint). */
 tg_status tg_readout_get_state(tg_readout* h, void* dst_dev, size_t bytes, void* hip_stream);

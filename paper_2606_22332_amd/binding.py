@@ -19,7 +19,8 @@ ABI_VERSION = 1
 
 TG_OUT_BITS, TG_OUT_DEPTH, TG_OUT_PROX, TG_OUT_FT = 1, 2, 4, 8
 TG_OUT_NOISY, TG_OUT_NORMAL, TG_OUT_SURFDIST, TG_OUT_LINK_SUMS = 16, 32, 64, 128
-OUT_ALL = 255
+TG_OUT_TEMP = 256
+OUT_ALL = 255                 # every readout output (TG_OUT_TEMP is added when the scene has fields)
 NSDF_NUM_PARAMS = 15681
 
 
@@ -41,6 +42,13 @@ class TgNoiseDesc(C.Structure):
                 ("eta_off", C.c_float)]
 
 
+class TgThermalDesc(C.Structure):
+    _fields_ = [("num_fields", C.c_int32), ("field_links", C.c_void_p), ("n", C.c_int32), ("dx", C.c_float),
+                ("origin", C.c_float * 3), ("dt", C.c_float), ("k_sensor", C.c_float), ("rho_cp", C.c_float),
+                ("emissivity", C.c_float), ("k_object", C.c_float), ("d_w", C.c_float), ("T0", C.c_float),
+                ("T_amb", C.c_float), ("P_gen", C.c_float), ("T_obj", C.c_void_p)]
+
+
 class TgReadoutConfig(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("num_envs", C.c_int32), ("num_links", C.c_int32),
                 ("num_taxels", C.c_int32), ("num_objects", C.c_int32), ("link_taxel_offset", C.c_void_p),
@@ -49,7 +57,7 @@ class TgReadoutConfig(C.Structure):
                 ("k_t", C.c_float), ("k_w", C.c_float), ("mu", C.c_float), ("prox_range", C.c_float),
                 ("eta_on", C.c_float), ("ft_spring_only", C.c_int32), ("noise_enabled", C.c_int32),
                 ("noise", TgNoiseDesc), ("output_mask", C.c_uint32), ("sdf_mode", C.c_int32),
-                ("nsdf_band", C.c_float), ("nsdf_params", C.c_void_p)]
+                ("nsdf_band", C.c_float), ("nsdf_params", C.c_void_p), ("thermal", C.c_void_p)]
 
 
 class TgStepInputs(C.Structure):
@@ -58,7 +66,7 @@ class TgStepInputs(C.Structure):
 
 class TgStepOutputs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("contact_bits", "contact_bits_noisy", "depth", "prox", "surfdist", "ft",
-                                         "ft_noisy", "normal", "link_sums", "link_sums_noisy")]
+                                         "ft_noisy", "normal", "link_sums", "link_sums_noisy", "temperature")]
 
 
 _lib = None
@@ -145,6 +153,20 @@ def make_config(scene, output_mask: int = OUT_ALL, keep: Optional[list] = None, 
     if not nz.enabled:
         output_mask &= ~TG_OUT_NOISY
     cfg.output_mask = output_mask
+    th = getattr(scene, "thermal", None)
+    if th is not None:
+        links = np.ascontiguousarray(th.field_links, np.int32)
+        tobj = np.ascontiguousarray(th.T_obj, np.float32)
+        assert tobj.shape == (scene.num_envs,)
+        td = TgThermalDesc()
+        td.num_fields, td.field_links, td.n, td.dx = len(links), links.ctypes.data, th.n, th.dx
+        td.origin[:] = [float(x) for x in th.origin]
+        td.dt, td.k_sensor, td.rho_cp, td.emissivity = th.dt, th.k_sensor, th.rho_cp, th.emissivity
+        td.k_object, td.d_w, td.T0, td.T_amb, td.P_gen = th.k_object, th.d_w, th.T0, th.T_amb, th.P_gen
+        td.T_obj = tobj.ctypes.data
+        keep += [links, tobj, td]
+        cfg.thermal = C.addressof(td)
+        cfg.output_mask |= TG_OUT_TEMP
     if nsdf_params is not None:      # torch float32 [num_objects, 15681] on the device
         assert nsdf_params.is_cuda and nsdf_params.is_contiguous()
         assert tuple(nsdf_params.shape) == (len(scene.grids), NSDF_NUM_PARAMS)
@@ -233,6 +255,8 @@ class Readout:
             o["link_sums"] = torch.zeros((steps, 11, E, L), **f32)
             if m & TG_OUT_NOISY:
                 o["link_sums_noisy"] = torch.zeros((steps, 11, E, L), **f32)
+        if m & TG_OUT_TEMP:
+            o["temperature"] = torch.zeros((steps, E, T), **f32)
         self.out = o
         self._out_steps = steps
         return o
@@ -242,7 +266,8 @@ class Readout:
             t = out.get(k)
             return None if t is None else t[s0].data_ptr()
         return TgStepOutputs(ptr("bits"), ptr("bits_noisy"), ptr("depth"), ptr("prox"), ptr("surfdist"), ptr("ft"),
-                             ptr("ft_noisy"), ptr("normal"), ptr("link_sums"), ptr("link_sums_noisy"))
+                             ptr("ft_noisy"), ptr("normal"), ptr("link_sums"), ptr("link_sums_noisy"),
+                             ptr("temperature"))
 
     def rollout(self, dinp: DeviceInputs, n_steps: Optional[int] = None, s_in: int = 0, s_out: int = 0,
                 out=None, stream=None):
@@ -282,6 +307,17 @@ class Readout:
     def set_state(self, buf, stream=None):
         _check(self.lib, self.h, self.lib.tg_readout_set_state(self.h, buf.data_ptr(), buf.numel() * buf.element_size(),
                                                                _stream_ptr(stream)), "set_state")
+
+    def thermal_fields(self):
+        """Copy of the temperature fields, torch float32 [E, F, 16, 16, 16] (z, y, x), or None."""
+        th = getattr(self.scene, "thermal", None)
+        if th is None:
+            return None
+        torch = self._torch
+        buf = torch.empty(self.state_size(), dtype=torch.uint8, device=self.device)
+        self.get_state(buf)
+        nb = self.E * len(th.field_links) * 16 ** 3 * 4
+        return buf[-nb:].view(torch.float32).reshape(self.E, len(th.field_links), 16, 16, 16).clone()
 
 
 def unpack_bits(words: np.ndarray, T: int) -> np.ndarray:

@@ -13,6 +13,7 @@
 #include "../../include/tg_readout.h"
 #include "link_kernel.h"
 #include "neural_kernel.h"
+#include "thermal_kernel.h"
 #include "nsdf_host.h"
 
 using namespace tg;
@@ -74,6 +75,11 @@ struct tg_readout {
   uint32_t* d_img = nullptr;
   int32_t* d_order = nullptr;
   size_t neural_lds = 0;
+  // thermal fields
+  int thermal = 0;
+  ThermalParams thp{};
+  ThermalParams* d_thp = nullptr;
+  size_t field_bytes = 0;
 };
 
 namespace {
@@ -268,6 +274,57 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     if (!(cfg->nsdf_band >= 0.f)) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "nsdf_band must be >= 0");
     if (neural_lds_bytes(L) > 160 * 1024) return fail(nullptr, TG_ERR_UNSUPPORTED, "too many links for the neural kernel");
   }
+  std::vector<int32_t> taxel_vox;
+  double th_r = 0, th_g = 0, th_rf = 0, th_kap = 0;
+  if (cfg->thermal) {
+    const tg_thermal_desc& td = *cfg->thermal;
+    if (cfg->sdf_mode != 0) return fail(nullptr, TG_ERR_UNSUPPORTED, "thermal fields need the grid SDF backend");
+    if (td.n != TH_N) return fail(nullptr, TG_ERR_UNSUPPORTED, "thermal fields must have 16 voxels per axis");
+    if (td.num_fields < 1 || !td.field_links || !td.T_obj)
+      return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "thermal: need fields, links and object temperatures");
+    if (!(td.dx > 0.f) || !(td.dt > 0.f) || !(td.k_sensor > 0.f) || !(td.rho_cp > 0.f) || !(td.k_object > 0.f) ||
+        !(td.emissivity >= 0.f) || !(td.d_w >= 0.f) || !(td.P_gen >= 0.f))
+      return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "thermal: bad material constants");
+    taxel_vox.assign(T, -1);
+    std::vector<int> per_vox;
+    int m_max = 0;
+    for (int f = 0; f < td.num_fields; ++f) {
+      const int l = td.field_links[f];
+      if (l < 0 || l >= L) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "thermal: field link out of range");
+      for (int f2 = 0; f2 < f; ++f2)
+        if (td.field_links[f2] == l) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "thermal: duplicate field link");
+      if (off[l + 1] - off[l] > 512) return fail(nullptr, TG_ERR_UNSUPPORTED, "thermal link with more than 512 taxels");
+      per_vox.assign(TH_N * TH_N, 0);
+      for (int j = off[l]; j < off[l + 1]; ++j) {
+        int idx[2];
+        for (int d = 0; d < 2; ++d) {
+          int i = (int)std::floor(((double)cfg->taxel_pos[3 * j + d] - (double)td.origin[d]) / (double)td.dx);
+          idx[d] = i < 0 ? 0 : (i > TH_N - 1 ? TH_N - 1 : i);
+        }
+        taxel_vox[j] = idx[1] * TH_N + idx[0];
+        m_max = std::max(m_max, ++per_vox[taxel_vox[j]]);
+      }
+    }
+    // derived constants (FP64, rounded once to FP32 for the kernel)
+    const double dx = td.dx, rc = td.rho_cp, dt = td.dt, Ta = (double)td.T_amb + 273.15;
+    const double alpha = (double)td.k_sensor / rc;
+    const double h_r = 4.0 * (double)td.emissivity * 5.670374419e-8 * Ta * Ta * Ta;
+    const double k_eff = 2.0 * (double)td.k_sensor * (double)td.k_object / ((double)td.k_sensor + (double)td.k_object);
+    th_r = alpha * dt / (dx * dx);
+    th_rf = dt * h_r / (rc * dx);
+    th_g = dt * (double)td.P_gen / ((double)TH_N * TH_N * TH_N * rc * dx * dx * dx);
+    th_kap = dt * 3.14159265358979323846 * (double)td.d_w * k_eff / (rc * dx * dx * dx);
+    // largest clean depth the grids allow: max R_j + max over objects of -min(phi)
+    double rmax = 0, dmin = 0;
+    for (int j = 0; j < T; ++j) rmax = std::max(rmax, (double)cfg->taxel_radius[j]);
+    for (int g = 0; g < NO; ++g) {
+      const tg_sdf_grid& G = cfg->grids[g];
+      const int64_t nv = (int64_t)G.n * G.n * G.n;
+      for (int64_t i = 0; i < nv; ++i) dmin = std::min(dmin, (double)G.values[i]);
+    }
+    if (!(6.0 * th_r + 3.0 * th_rf + th_kap * (rmax - dmin) * (double)m_max <= 1.0))
+      return fail(nullptr, TG_ERR_UNSTABLE, "thermal step not stable: 6 r + 3 rho_f + kappa d_max m > 1");
+  }
 
   tg_readout* h = new (std::nothrow) tg_readout();
   if (!h) return fail(nullptr, TG_ERR_OUT_OF_MEMORY, "host allocation");
@@ -458,6 +515,40 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
       return fail(nullptr, TG_ERR_HIP, std::string("neural SDF setup: ") + hipGetErrorString(e));
     }
   }
+  if (cfg->thermal) {
+    const tg_thermal_desc& td = *cfg->thermal;
+    h->thermal = 1;
+    ThermalParams& tp = h->thp;
+    int32_t *dLinks = nullptr, *dVox = nullptr;
+    float *dTobj = nullptr, *dF = nullptr;
+    const int F = td.num_fields;
+    h->field_bytes = (size_t)E * F * TH_N * TH_N * TH_N * sizeof(float);
+    e = dalloc(h, &dLinks, F);
+    if (e == hipSuccess) e = dalloc(h, &dVox, T);
+    if (e == hipSuccess) e = dalloc(h, &dTobj, E);
+    if (e == hipSuccess) e = dalloc(h, &dF, (size_t)E * F * TH_N * TH_N * TH_N);
+    if (e == hipSuccess) e = dalloc(h, &h->d_thp, 1);
+    if (e == hipSuccess) e = hipMemcpy(dLinks, td.field_links, F * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dVox, taxel_vox.data(), T * sizeof(int32_t), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dTobj, td.T_obj, E * sizeof(float), hipMemcpyHostToDevice);
+    tp.F = F;
+    tp.field_link = dLinks;
+    tp.taxel_vox = dVox;
+    tp.T_obj = dTobj;
+    tp.fields = dF;
+    tp.r = (float)th_r;
+    tp.g = (float)th_g;
+    tp.rho_f = (float)th_rf;
+    tp.kappa = (float)th_kap;
+    tp.T_amb = td.T_amb;
+    tp.T0 = td.T0;
+    if (e == hipSuccess) e = hipMemcpy(h->d_thp, &tp, sizeof(ThermalParams), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      tg_readout_destroy(h);
+      return fail(nullptr, TG_ERR_HIP, std::string("thermal setup: ") + hipGetErrorString(e));
+    }
+    h->state_bytes += h->field_bytes;
+  }
   tg_status st = tg_readout_reset(h, nullptr, 0, nullptr);
   if (st == TG_OK) {
     e = hipDeviceSynchronize();
@@ -481,6 +572,11 @@ tg_status tg_readout_reset(tg_readout* h, const uint8_t* env_mask_dev, int64_t s
   const int blocks = (int)((ET + threads - 1) / threads);
   hipLaunchKernelGGL(tg_reset_kernel, dim3(blocks), dim3(threads), 0, (hipStream_t)hip_stream, h->kp, env_mask_dev,
                      step, h->stuck_lo, h->stuck_span, h->gain_lo, h->gain_span, h->dead_thr);
+  if (h->thermal) {
+    const int64_t nf = (int64_t)h->E * h->thp.F * TH_N * TH_N * TH_N;
+    hipLaunchKernelGGL(tg_thermal_reset_kernel, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)hip_stream, (const ThermalParams*)h->d_thp, h->E, env_mask_dev);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(h, TG_ERR_HIP, std::string("reset launch: ") + hipGetErrorString(e));
   return TG_OK;
@@ -504,13 +600,15 @@ tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_s
       {out->prox, TG_OUT_PROX, "prox"},                     {out->ft, TG_OUT_FT, "ft"},
       {out->ft_noisy, TG_OUT_NOISY, "ft_noisy"},            {out->contact_bits_noisy, TG_OUT_NOISY, "contact_bits_noisy"},
       {out->normal, TG_OUT_NORMAL, "normal"},               {out->surfdist, TG_OUT_SURFDIST, "surfdist"},
-      {out->link_sums, TG_OUT_LINK_SUMS, "link_sums"}};
+      {out->link_sums, TG_OUT_LINK_SUMS, "link_sums"},     {out->temperature, TG_OUT_TEMP, "temperature"}};
   for (const Req& r : req) {
     const bool want = (om & r.bit) != 0;
     if (want && !r.p) return fail(h, TG_ERR_INVALID_ARGUMENT, std::string(r.name) + " requested but NULL");
     if (!want && r.p) return fail(h, TG_ERR_INVALID_ARGUMENT, std::string(r.name) + " not requested but non-NULL");
     if (r.p && !aligned(r.p, 16)) return fail(h, TG_ERR_INVALID_ARGUMENT, std::string(r.name) + " misaligned");
   }
+  if ((om & TG_OUT_TEMP) && !h->thermal)
+    return fail(h, TG_ERR_INVALID_ARGUMENT, "temperature requested without thermal fields");
   const bool want_ln = (om & TG_OUT_LINK_SUMS) && (om & TG_OUT_NOISY);
   if (want_ln != (out->link_sums_noisy != nullptr))
     return fail(h, TG_ERR_INVALID_ARGUMENT, "link_sums_noisy must be set iff LINK_SUMS and NOISY are requested");
@@ -561,6 +659,18 @@ tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_s
   k.normal = out->normal; k.link_sums = out->link_sums; k.link_sums_noisy = out->link_sums_noisy;
   KernelFn kf = select_kernel(h->noise, h->xt, h->hy, in->obj_state ? 1 : 0, h->full);
   hipLaunchKernelGGL(kf, dim3(h->kp.n_items_pad), dim3(h->threads), h->lds, (hipStream_t)hip_stream, k);
+  if (h->thermal) {
+    ThermalLaunch t{};
+    t.kc = h->d_kp;
+    t.th = h->d_thp;
+    t.n_steps = n_steps;
+    t.link_state = in->link_state;
+    t.obj_state = in->obj_state;
+    t.obj_id = in->obj_id;
+    t.temperature = out->temperature;
+    hipLaunchKernelGGL(tg_thermal_kernel, dim3((unsigned)(h->E * h->thp.F)), dim3(TH_THREADS), 0,
+                       (hipStream_t)hip_stream, t);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(h, TG_ERR_HIP, std::string("readout launch: ") + hipGetErrorString(e));
   return TG_OK;
@@ -584,9 +694,10 @@ static tg_status copy_state(tg_readout* h, void* buf, size_t bytes, bool to_buf,
   struct Part { void* p; size_t n; } parts[] = {
       {h->kp.drift, 6 * ET * 4}, {h->kp.hyst, 6 * ET * 4}, {h->kp.hyst_prev, 6 * ET * 4},
       {h->kp.stuck, ET * 4},     {h->kp.gain, ET * 4},     {h->kp.schmitt, ET},
-      {h->kp.dead, ET}};
+      {h->kp.dead, ET},          {h->thermal ? (void*)h->thp.fields : nullptr, h->field_bytes}};
   size_t off = 0;
   for (const Part& pt : parts) {
+    if (!pt.p || pt.n == 0) continue;
     char* b = (char*)buf + off;
     hipError_t e = to_buf ? hipMemcpyAsync(b, pt.p, pt.n, hipMemcpyDeviceToDevice, (hipStream_t)stream)
                           : hipMemcpyAsync(pt.p, b, pt.n, hipMemcpyDeviceToDevice, (hipStream_t)stream);

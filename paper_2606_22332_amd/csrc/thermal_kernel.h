@@ -1,0 +1,152 @@
+// Voxel temperature fields on the thermal links, integrated with the readout's rollout.
+//
+// One workgroup per field (env, thermal link), persistent over the launch's steps; each of its
+// n*n = 256 threads owns one z-column of the 16^3 block and keeps it in registers for the whole
+// rollout, so the field touches HBM only when the launch starts and ends.  Per step:
+//   1. the link's taxels recompute their clean depth with the readout's own FP32 sequence (probe
+//      point, grid lookup, d = [R_j - phi]_+), so the heat input uses exactly the depths the
+//      readout reports;
+//   2. each top-layer column sums kappa * d over the taxels above it, in taxel order;
+//   3. columns exchange their values through LDS and apply the explicit step
+//        s   = ((T[x-1] + T[x+1]) + (T[y-1] + T[y+1])) + (T[z-1] + T[z+1])   (mirrored faces)
+//        src = (g + rho_f * faces * (T_amb - T)) [+ c_v * (T_obj - T) on the top layer]
+//        T'  = T + (r * (s - 6 T) + src);
+//   4. the temperature of the top-layer voxel under each taxel is written out.
+#pragma once
+#include "readout_kernel.h"
+
+namespace tg {
+
+constexpr int TH_N = 16;                 // voxels per axis handled by this kernel
+constexpr int TH_THREADS = TH_N * TH_N;  // one thread per (x, y) column
+
+struct ThermalParams {
+  int32_t F;                   // fields per env
+  const int32_t* field_link;   // [F]
+  const int32_t* taxel_vox;    // [T] top-layer voxel (y * n + x) of thermal taxels, -1 otherwise
+  const float* T_obj;          // [E]
+  float* fields;               // [E][F][n^3], index ((z * n) + y) * n + x
+  float r, g, rho_f, kappa, T_amb, T0;
+};
+
+struct ThermalLaunch {
+  const KParams* kc;
+  const ThermalParams* th;
+  int32_t n_steps;
+  const float* link_state;     // [S][13][E*L]
+  const float* obj_state;      // [S][13][E] or null
+  const int32_t* obj_id;       // [S][E]
+  float* temperature;          // [S][E][T] or null
+};
+
+__global__ __launch_bounds__(TH_THREADS) void tg_thermal_kernel(const ThermalLaunch q) {
+  constexpr int n = TH_N;
+  const KParams& p = *q.kc;
+  const ThermalParams& th = *q.th;
+  const int e = blockIdx.x / th.F, f = blockIdx.x - e * th.F;
+  const int l = th.field_link[f];
+  const int tid = threadIdx.x, x = tid % n, y = tid / n;
+  const int E = p.E, L = p.L, T = p.T;
+  const int64_t EL = (int64_t)E * L, ET = (int64_t)E * T;
+  __shared__ float ex[n * n * n];          // exchange buffer [z][y][x]
+  __shared__ float cd[512];                // kappa * depth per taxel of the link
+  __shared__ float top[n * n];
+  __shared__ Pose lp, op;
+  __shared__ int oid_s;
+  float* fld = th.fields + ((int64_t)e * th.F + f) * (n * n * n);
+  float col[n];
+#pragma unroll
+  for (int z = 0; z < n; ++z) col[z] = fld[(z * n + y) * n + x];
+  const int jb = __ldg(&p.link_off[l]), je = __ldg(&p.link_off[l + 1]);
+  const int nl = je - jb;
+  const float Tobj = th.T_obj[e];
+  const float r = th.r, g = th.g, rf = th.rho_f, Tamb = th.T_amb;
+  const int fxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
+  const int myvox = y * n + x;
+  for (int s = 0; s < q.n_steps; ++s) {
+    // 1. poses of this step
+    if (tid == 0) {
+      const float* ls = q.link_state + (int64_t)s * 13 * EL;
+      const int64_t c = (int64_t)e * L + l;
+      lp.p[0] = ls[0 * EL + c]; lp.p[1] = ls[1 * EL + c]; lp.p[2] = ls[2 * EL + c];
+      quat_to_R(ls[3 * EL + c], ls[4 * EL + c], ls[5 * EL + c], ls[6 * EL + c], lp.R);
+      oid_s = q.obj_id[(int64_t)s * E + e];
+    }
+    if (q.obj_state && tid == 1) {
+      const float* os = q.obj_state + (int64_t)s * 13 * E;
+      op.p[0] = os[0 * E + e]; op.p[1] = os[1 * E + e]; op.p[2] = os[2 * E + e];
+      quat_to_R(os[3 * E + e], os[4 * E + e], os[5 * E + e], os[6 * E + e], op.R);
+    }
+#pragma unroll
+    for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];
+    __syncthreads();
+    // 2. clean depth of the link's taxels (same sequence as the readout)
+    for (int k = tid; k < nl; k += TH_THREADS) {
+      const int j = jb + k;
+      const float4 ta = p.taxA[j];
+      float d = 0.f;
+      const int oid = oid_s;
+      if (oid >= 0 && oid < p.n_obj && ta.w > 0.f) {
+        const float xj[3] = {ta.x, ta.y, ta.z};
+        float qw[3], qo[3];
+        probe_point(lp, q.obj_state ? &op : nullptr, xj, qw, qo);
+        GridHit h;
+        grid_lookup(p.grids[oid], p.grid_vals, qo, h);
+        if (!h.far) {
+          const float diff = ta.w - h.phi;
+          d = diff > 0.f ? diff : 0.f;
+        }
+      }
+      cd[k] = th.kappa * d;
+    }
+    __syncthreads();
+    // 3. contact coefficient of this column's top voxel, in taxel order
+    float cv = 0.f;
+    for (int k = 0; k < nl; ++k)
+      if (th.taxel_vox[jb + k] == myvox) cv = cv + cd[k];
+    // 4. explicit step from the old values (exchange buffer and registers), into registers
+    float nc[n];
+#pragma unroll
+    for (int z = 0; z < n; ++z) {
+      const float t = col[z];
+      const float xm = x > 0 ? ex[(z * n + y) * n + x - 1] : t;
+      const float xp = x < n - 1 ? ex[(z * n + y) * n + x + 1] : t;
+      const float ym = y > 0 ? ex[(z * n + y - 1) * n + x] : t;
+      const float yp = y < n - 1 ? ex[(z * n + y + 1) * n + x] : t;
+      const float zm = z > 0 ? col[z - 1] : t;
+      const float zp = z < n - 1 ? col[z + 1] : t;
+      const float sum = ((xm + xp) + (ym + yp)) + (zm + zp);
+      const int faces = fxy + (z == 0) + (z == n - 1);
+      const float rfx = rf * (float)faces;
+      float src = g + rfx * (Tamb - t);
+      if (z == n - 1) src = src + cv * (Tobj - t);
+      nc[z] = t + (r * (sum - 6.0f * t) + src);
+    }
+#pragma unroll
+    for (int z = 0; z < n; ++z) col[z] = nc[z];
+    top[myvox] = col[n - 1];
+    __syncthreads();   // every read of ex and cd is done; top is complete
+    if (q.temperature) {
+      float* out = q.temperature + (int64_t)s * ET + (int64_t)e * T;
+      for (int k = tid; k < nl; k += TH_THREADS) out[jb + k] = top[th.taxel_vox[jb + k]];
+      if (f == 0)   // the first field's workgroup clears the taxels of the non-thermal links
+        for (int j = tid; j < T; j += TH_THREADS)
+          if (th.taxel_vox[j] < 0) out[j] = 0.f;
+    }
+  }
+#pragma unroll
+  for (int z = 0; z < n; ++z) fld[(z * n + y) * n + x] = col[z];
+}
+
+__global__ void tg_thermal_reset_kernel(const ThermalParams* thp, int E, const uint8_t* mask) {
+  const ThermalParams& th = *thp;
+  const int64_t NV = (int64_t)TH_N * TH_N * TH_N;
+  const int64_t total = (int64_t)E * th.F * NV;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int e = (int)(i / (th.F * NV));
+  if (mask && !mask[e]) return;
+  th.fields[i] = th.T0;
+}
+
+}  // namespace tg

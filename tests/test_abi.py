@@ -55,3 +55,19 @@ def test_binding_raises_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(binding.TgError):
         binding.load()
+
+
+def test_unstable_thermal_configuration_is_rejected_at_create():
+    """The positivity bound of the explicit thermal step is checked before any device work."""
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+    import ctypes as C
+    sc = synth.make_scene("c5", num_envs=2, num_steps=1)
+    sc.thermal.dt = 2.0                     # r = alpha dt / dx^2 = 0.2 > 1/6
+    lib = B.load()
+    keep = []
+    cfg = B.make_config(sc, B.OUT_ALL, keep)
+    h = C.c_void_p()
+    rc = lib.tg_readout_create(C.byref(cfg), C.byref(h))
+    assert rc == 5 and not h.value             # TG_ERR_UNSTABLE
+    assert b"stable" in lib.tg_readout_last_error(None)

@@ -79,7 +79,13 @@ def test_targets_match_oracle(torch_cuda, grids):
         assert np.all(np.abs(rec[o, :, :3]) <= 1.0)
 
 
-@pytest.mark.parametrize("counts", [[1, 37, 300], [0, 64, 129]])
+def angle_deg(a, b):
+    """Angle between rows of a and b in FP64 (atan2 form: accurate for tiny angles)."""
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    return np.degrees(np.arctan2(np.linalg.norm(np.cross(a, b), axis=-1), np.sum(a * b, axis=-1)))
+
+
+@pytest.mark.parametrize("counts", [[1, 37, 3000], [0, 64, 2049]])
 def test_query_matches_bf16_oracle(torch_cuda, grids, counts):
     torch = torch_cuda
     from paper_2606_22332_amd import binding as B
@@ -99,25 +105,23 @@ def test_query_matches_bf16_oracle(torch_cuda, grids, counts):
     out, gx, out2 = out.cpu().numpy(), gx.cpu().numpy(), out2.cpu().numpy()
     ns.close()
     assert np.array_equal(out, out2)
+    errs, angs, rels = [], [], []
     for o, g in enumerate(gs):
         sl = slice(offs[o], offs[o + 1])
         if counts[o] == 0:
             continue
         ref, rg = oracle.nsdf_forward(P[o].astype(np.float64), X[sl].astype(np.float64), grad=True, bf16=True)
-        e = half_extent(g)
-        err_um = np.abs(out[sl] - ref) * e * 1e6
+        errs.append(np.abs(out[sl] - ref) * half_extent(g) * 1e6)
+        angs.append(angle_deg(gx[sl], rg))
         nr = np.linalg.norm(rg, axis=1)
-        ng = np.linalg.norm(gx[sl], axis=1)
-        cosang = np.sum(rg * gx[sl], axis=1) / np.maximum(nr * ng, 1e-30)
-        ang = np.degrees(np.arccos(np.clip(cosang, -1, 1)))
-        rel = np.abs(ng - nr) / np.maximum(nr, 1e-30)
-        stats = dict(obj=o, phi_p999_um=np.quantile(err_um, 0.999), phi_max_um=err_um.max(),
-                     ang_p99=np.quantile(ang, 0.99), ang_max=ang.max(), gnorm_rel_max=rel.max(),
-                     worst_gnorm_over_median=float(nr[np.argmax(ang)] / np.median(nr)))
-        print(stats)
-        assert stats["phi_p999_um"] <= 20.0 and stats["phi_max_um"] <= 200.0, stats
-        assert stats["ang_p99"] <= 0.1 and stats["ang_max"] <= 1.0, stats
-        assert np.quantile(rel, 0.99) <= 1e-2, stats
+        rels.append(np.abs(np.linalg.norm(gx[sl].astype(np.float64), axis=1) - nr) / np.maximum(nr, 1e-30))
+    err_um, ang, rel = np.concatenate(errs), np.concatenate(angs), np.concatenate(rels)
+    stats = dict(n=len(ang), phi_p999_um=np.quantile(err_um, 0.999), phi_max_um=err_um.max(),
+                 ang_p99=np.quantile(ang, 0.99), ang_max=ang.max(), gnorm_rel_p99=np.quantile(rel, 0.99))
+    print(stats)
+    assert stats["phi_p999_um"] <= 20.0 and stats["phi_max_um"] <= 200.0, stats
+    assert stats["ang_p99"] <= 0.1 and stats["ang_max"] <= 1.0, stats
+    assert stats["gnorm_rel_p99"] <= 1e-2, stats
 
 
 def layer_rel(a, b):
@@ -165,9 +169,10 @@ def test_adam_matches_oracle(torch_cuda):
     torch.cuda.synchronize()
     ns.close()
     P64, m64, v64 = P.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
-    oracle.nsdf_adam(P64, m64, v64, g.astype(np.float64), 7, lr=1e-3)
+    # the library holds the hyperparameters in FP32: give the oracle the same values
+    b1, b2, lr, eps = (float(np.float32(x)) for x in (0.9, 0.999, 1e-3, 1e-8))
+    oracle.nsdf_adam(P64, m64, v64, g.astype(np.float64), 7, lr=lr, b1=b1, b2=b2, eps=eps)
     # FP32 against FP64: each result within a few FP32 ulps of the magnitude of what was summed
-    b1, b2 = 0.9, 0.999
     sm = b1 * np.abs(m) + (1 - b1) * np.abs(g)
     sv = b2 * np.abs(v) + (1 - b2) * g.astype(np.float64) ** 2
     assert np.all(np.abs(dm.cpu().numpy() - m64) <= 4e-7 * sm + 1e-30)

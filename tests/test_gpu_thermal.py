@@ -1,0 +1,86 @@
+"""Thermal fields fused into the readout rollout, against the CPU oracle through the C ABI.
+
+The kernel recomputes each thermal taxel's clean depth with the readout's FP32 sequence and applies
+the same written FP32 update as the oracle's float build, so both the per-step taxel temperatures
+and the fields after the rollout must equal the oracle bit for bit; the readout outputs of the same
+rollout keep their own parity bar.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import parity
+from paper_2606_22332_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def c5_scene(E=12, S=40, dt=None):
+    sc = synth.make_scene("c5", num_envs=E, num_steps=S)
+    if dt is not None:          # a longer step makes the fields move enough to see in a few steps
+        sc.thermal.dt = dt
+    return sc
+
+
+def oracle_thermal(sc, inp, ref_depth, fields=None):
+    return oracle.thermal_run(sc.thermal, sc.layout, ref_depth, fields=fields, precision="f32")
+
+
+@pytest.mark.parametrize("dt", [None, 0.05])
+def test_fields_and_taxel_temperatures_match_oracle(torch_cuda, dt):
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    sc = c5_scene(dt=dt)
+    inp = synth.make_inputs(sc)
+    oid = inp.obj_id.copy(); oid[:, 2] = -1; inp.obj_id = oid          # an env without object
+    S = inp.link_state.shape[0]
+    ro = B.Readout(sc)
+    ro.alloc_outputs(S)
+    ro.rollout(B.to_device(inp), S)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in ro.out.items()}
+    fields = ro.thermal_fields().cpu().numpy()
+    ro.out = {}
+    ro.close()
+    ref = oracle.run_readout(sc, inp, precision="f32")
+    parity.compare({k: v for k, v in g.items() if k != "temperature"}, ref, sc.layout.num_taxels, noisy=True,
+                   sigma=sc.noise.drift_sigma, link_offset=sc.layout.link_offset)
+    f_ref, tt_ref, _ = oracle_thermal(sc, inp, ref["depth"])
+    d_t = np.abs(g["temperature"].astype(np.float64) - tt_ref)
+    d_f = np.abs(fields.astype(np.float64) - f_ref.astype(np.float64))
+    print(dict(max_taxel_diff=float(d_t.max()), max_field_diff=float(d_f.max()),
+               field_range=(float(f_ref.min()), float(f_ref.max()))))
+    assert d_t.max() == 0.0 and d_f.max() == 0.0
+    assert float(f_ref.max() - f_ref.min()) > 0.0
+
+
+def test_reset_and_state_roundtrip(torch_cuda):
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    sc = c5_scene(E=8, S=10, dt=0.05)
+    inp = synth.make_inputs(sc)
+    ro = B.Readout(sc)
+    ro.alloc_outputs(10)
+    d = B.to_device(inp)
+    ro.rollout(d, 10)
+    f1 = ro.thermal_fields()
+    buf = torch.empty(ro.state_size(), dtype=torch.uint8, device="cuda")
+    ro.get_state(buf)
+    mask = torch.zeros(8, dtype=torch.uint8, device="cuda"); mask[[1, 5]] = 1
+    ro.reset(mask, step=10)
+    f2 = ro.thermal_fields()
+    assert torch.all(f2[[1, 5]] == sc.thermal.T0)
+    keep = [0, 2, 3, 4, 6, 7]
+    assert torch.equal(f2[keep], f1[keep])
+    ro.set_state(buf)
+    assert torch.equal(ro.thermal_fields(), f1)
+    ro.out = {}
+    ro.close()
