@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--config", default="c3")
     ap.add_argument("--envs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -95,10 +97,15 @@ def main():
     if sc.noise.enabled:
         mask |= B.TG_OUT_NOISY
     ro = B.Readout(sc, mask)
+    if args.no_graph:
+        ro.set_graph(False)
     dinp = B.to_device(inp)
     ro.alloc_outputs(S)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
+    tuned = None
+    if not args.no_autotune:
+        tuned = ro.autotune(dinp, S)
 
     # rollouts continue one another (the step counter advances by S each time), as in a long
     # simulation; the noise state carries over on the device
@@ -135,10 +142,11 @@ def main():
                                + ("noisy, " + {0: "no", 1: "banded", 2: "dense BF16-MFMA"}[sc.noise.xtalk_kind]
                                   + " crosstalk" if sc.noise.enabled else "clean"),
                    "envs": E, "taxels": T, "links": L, "steps_per_rollout": S,
-                   "envs_per_block": eb, "threads_per_block": threads},
+                   "readouts_per_block_target": eb, "threads_per_block": threads,
+                   "autotuned": tuned is not None, "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "tg_readout_kernel", "algorithmic_bytes_per_launch": nbytes,
+                     "kernel": "tg_link_kernel", "algorithmic_bytes_per_launch": nbytes,
                      "bytes_per_readout": nbytes / readouts, "kernel_ms_mean": ms,
                      "kernel_ms_min": float(np.min(kernel_ms))},
         "input_gen_s": gen_s,

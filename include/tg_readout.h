@@ -214,6 +214,20 @@ tg_status tg_readout_set_state(tg_readout* h, const void* src_dev, size_t bytes,
 /* Kernel launch shape the handle uses (for profiling tools): envs per block and threads. */
 tg_status tg_readout_launch_shape(const tg_readout* h, int32_t* envs_per_block, int32_t* threads);
 
+/* Graph mode (default on): rollout records its kernel launches once into a HIP graph on a
+ * private stream and replays the graph on `hip_stream`, updating only the launch arguments on
+ * later calls.  When `hip_stream` is itself being captured the plain launches are issued
+ * instead, so a caller can capture rollout into its own graph. */
+tg_status tg_readout_set_graph(tg_readout* h, int32_t enable);
+
+/* Autotuner for the readout kernel's work plan (readouts per workgroup: 192, 256, 384, 512).
+ * Runs each candidate on the caller's inputs and outputs for n_steps steps, keeps the
+ * fastest plan for this handle and reports it.  Unlike step/rollout it allocates a state
+ * buffer, synchronises and overwrites `out`; the dynamic state is restored afterwards.  The
+ * neural backend has no plan to tune (best_target = 0). */
+tg_status tg_readout_autotune(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, int32_t n_steps,
+                              void* hip_stream, int32_t* best_target, float* best_ms);
+
 /* Release the handle and its device memory (synchronises the device). NULL is accepted. */
 tg_status tg_readout_destroy(tg_readout* h);
 

@@ -90,6 +90,8 @@ def load() -> C.CDLL:
         "tg_readout_get_state": ([P, P, C.c_size_t, P], C.c_int),
         "tg_readout_set_state": ([P, P, C.c_size_t, P], C.c_int),
         "tg_readout_launch_shape": ([P, P, P], C.c_int),
+        "tg_readout_set_graph": ([P, C.c_int32], C.c_int),
+        "tg_readout_autotune": ([P, P, P, C.c_int32, P, P, P], C.c_int),
         "tg_readout_destroy": ([P], C.c_int),
         "tg_readout_last_error": ([P], C.c_char_p),
         "tg_status_string": ([C.c_int], C.c_char_p),
@@ -307,6 +309,23 @@ class Readout:
     def set_state(self, buf, stream=None):
         _check(self.lib, self.h, self.lib.tg_readout_set_state(self.h, buf.data_ptr(), buf.numel() * buf.element_size(),
                                                                _stream_ptr(stream)), "set_state")
+
+    def set_graph(self, enable: bool):
+        _check(self.lib, self.h, self.lib.tg_readout_set_graph(self.h, int(bool(enable))), "set_graph")
+
+    def autotune(self, dinp: DeviceInputs, n_steps: Optional[int] = None, stream=None):
+        """Time the candidate work plans on these inputs (outputs are overwritten, state restored);
+        returns (readouts per workgroup, ms of the best rollout)."""
+        S = dinp.link_state.shape[0] if n_steps is None else n_steps
+        ist = TgStepInputs(dinp.link_state[0].data_ptr(),
+                           None if dinp.obj_state is None else dinp.obj_state[0].data_ptr(),
+                           dinp.obj_id[0].data_ptr(), dinp.step0)
+        ost = self._outputs_struct(self.out, 0)
+        best, ms = C.c_int32(), C.c_float()
+        rc = self.lib.tg_readout_autotune(self.h, C.byref(ist), C.byref(ost), int(S), _stream_ptr(stream),
+                                          C.byref(best), C.byref(ms))
+        _check(self.lib, self.h, rc, "tg_readout_autotune")
+        return best.value, ms.value
 
     def thermal_fields(self):
         """Copy of the temperature fields, torch float32 [E, F, 16, 16, 16] (z, y, x), or None."""

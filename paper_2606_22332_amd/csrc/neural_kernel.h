@@ -110,6 +110,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
   const Img im = img_at(smem);
   const int64_t EL = (int64_t)E * L, ET = (int64_t)E * T;
   int loaded = -1;
+#pragma unroll 1
   for (int k = 0; k < NEU_ENVS; ++k) {
     const int idx = blockIdx.x * NEU_ENVS + k;
     if (idx >= E) break;                                   // uniform
@@ -133,6 +134,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
       gd = p.grids[oid];
       bx = q.boxes[oid];
     }
+#pragma unroll 1
     for (int grp = wave; grp * 64 < T; grp += NEU_THREADS / 64) {
       const int j0 = grp * 64;
       // ---- tile phase ----
@@ -230,6 +232,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
         const float v[10] = {o.f[0], o.f[1], o.f[2], o.tau[0], o.tau[1], o.tau[2], bit ? 1.f : 0.f,
                              o.depth * tb.z, o.depth * tb.y, o.depth * tb.x};
         unsigned long long left = __ballot(valid);
+#pragma unroll 1
         while (left) {                                     // one pass per link present in the wave
           const int lead = __ffsll((long long)left) - 1;
           const int lk = __shfl(l, lead);

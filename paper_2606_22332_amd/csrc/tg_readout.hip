@@ -75,6 +75,10 @@ struct tg_readout {
   uint32_t* d_img = nullptr;
   int32_t* d_order = nullptr;
   size_t neural_lds = 0;
+  // launch graph of the rollout (recorded on a private stream, replayed on the caller's)
+  int graph_on = 1;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
   // thermal fields
   int thermal = 0;
   ThermalParams thp{};
@@ -140,6 +144,12 @@ tg_status plan_links(tg_readout* h, int target) {
     li.kpd = n16 + 4;
     nthr = std::max(nthr, ((li.envs * li.n + 63) / 64) * 64);
   }
+  {  // the per-step input prefetch parks 14 scalars per env, one per lane
+    int max_envs = 1;
+    for (int l = 0; l < L; ++l) max_envs = std::max(max_envs, h->links[l].envs);
+    nthr = std::max(nthr, ((14 * max_envs + 63) / 64) * 64);
+  }
+  if (nthr > 512) return TG_ERR_UNSUPPORTED;
   h->threads = nthr;
   // LDS layout: max over links of each region
   int64_t pose = 0, bits = 0, bt = 0, dt = 0, tax = 0;
@@ -219,6 +229,8 @@ const char* tg_readout_last_error(const tg_readout* h) { return h ? h->err.c_str
 tg_status tg_readout_destroy(tg_readout* h) {
   if (!h) return TG_OK;
   (void)hipDeviceSynchronize();
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   for (void* p : h->allocs) (void)hipFree(p);
   for (void* p : h->xtd.allocs) (void)hipFree(p);
   delete h;
@@ -549,6 +561,11 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     }
     h->state_bytes += h->field_bytes;
   }
+  e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    tg_readout_destroy(h);
+    return fail(nullptr, TG_ERR_HIP, std::string("stream: ") + hipGetErrorString(e));
+  }
   tg_status st = tg_readout_reset(h, nullptr, 0, nullptr);
   if (st == TG_OK) {
     e = hipDeviceSynchronize();
@@ -581,6 +598,9 @@ tg_status tg_readout_reset(tg_readout* h, const uint8_t* env_mask_dev, int64_t s
   if (e != hipSuccess) return fail(h, TG_ERR_HIP, std::string("reset launch: ") + hipGetErrorString(e));
   return TG_OK;
 }
+
+static tg_status launch_rollout(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, int32_t n_steps,
+                                hipStream_t stream);
 
 tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, int32_t n_steps,
                              void* hip_stream) {
@@ -615,6 +635,50 @@ tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_s
   if (out->link_sums_noisy && !aligned(out->link_sums_noisy, 16))
     return fail(h, TG_ERR_INVALID_ARGUMENT, "link_sums_noisy misaligned");
 
+  // Graph mode: record this call's launches on the private stream, then update the cached
+  // executable graph (same kernels and shapes: only the arguments change) and replay it on the
+  // caller's stream.  A caller that is itself capturing gets the plain launches.
+  hipStream_t target = (hipStream_t)hip_stream;
+  bool use_graph = h->graph_on != 0;
+  if (use_graph) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(target, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) use_graph = false;
+  }
+  hipStream_t ls = use_graph ? h->cap : target;
+  if (use_graph) {
+    const hipError_t ce = hipStreamBeginCapture(ls, hipStreamCaptureModeThreadLocal);
+    if (ce != hipSuccess) return fail(h, TG_ERR_HIP, std::string("graph capture: ") + hipGetErrorString(ce));
+  }
+  tg_status lst = launch_rollout(h, in, out, n_steps, ls);
+  if (use_graph) {
+    hipGraph_t g = nullptr;
+    const hipError_t ee = hipStreamEndCapture(ls, &g);
+    if (ee != hipSuccess || lst != TG_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return lst != TG_OK ? lst : fail(h, TG_ERR_HIP, std::string("graph capture end: ") + hipGetErrorString(ee));
+    }
+    if (h->gexec) {
+      hipGraphNode_t en = nullptr;
+      hipGraphExecUpdateResult ur;
+      if (hipGraphExecUpdate(h->gexec, g, &en, &ur) != hipSuccess || ur != hipGraphExecUpdateSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphExecDestroy(h->gexec);
+        h->gexec = nullptr;
+      }
+    }
+    hipError_t ge = hipSuccess;
+    if (!h->gexec) ge = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ge == hipSuccess) ge = hipGraphLaunch(h->gexec, target);
+    if (ge != hipSuccess) return fail(h, TG_ERR_HIP, std::string("graph launch: ") + hipGetErrorString(ge));
+    return TG_OK;
+  }
+  return lst;
+}
+
+static tg_status launch_rollout(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, int32_t n_steps,
+                                hipStream_t stream) {
+  void* hip_stream = (void*)stream;
   if (h->neural) {
     const int64_t EL = (int64_t)h->E * h->L, ET = (int64_t)h->E * h->T;
     hipStream_t st = (hipStream_t)hip_stream;
@@ -678,6 +742,73 @@ tg_status tg_readout_rollout(tg_readout* h, const tg_step_inputs* in, const tg_s
 
 tg_status tg_readout_step(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, void* hip_stream) {
   return tg_readout_rollout(h, in, out, 1, hip_stream);
+}
+
+tg_status tg_readout_set_graph(tg_readout* h, int32_t enable) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  h->graph_on = enable != 0;
+  return TG_OK;
+}
+
+tg_status tg_readout_autotune(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, int32_t n_steps,
+                              void* hip_stream, int32_t* best_target, float* best_ms) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  h->err.clear();
+  if (n_steps < 1) return fail(h, TG_ERR_INVALID_ARGUMENT, "autotune needs n_steps >= 1");
+  if (h->neural) {   // the neural kernel has no plan to tune
+    if (best_target) *best_target = 0;
+    if (best_ms) *best_ms = 0.f;
+    return TG_OK;
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  void* saved = nullptr;
+  hipError_t e = hipMalloc(&saved, std::max<size_t>(h->state_bytes, 1));
+  if (e != hipSuccess) return fail(h, TG_ERR_OUT_OF_MEMORY, "autotune: state buffer");
+  tg_status rs = tg_readout_get_state(h, saved, h->state_bytes, hip_stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  const int cand[] = {192, 256, 384, 512};
+  int best = h->target;
+  float bms = 3.4e38f;
+  for (int c : cand) {
+    if (rs != TG_OK) break;
+    if (hipStreamSynchronize(st) != hipSuccess) { rs = TG_ERR_HIP; break; }
+    if (plan_links(h, c) != TG_OK || h->lds > 160 * 1024) continue;
+    if (hipMemcpy(h->d_kp, &h->kp, sizeof(KParams), hipMemcpyHostToDevice) != hipSuccess) { rs = TG_ERR_HIP; break; }
+    KernelFn kf = select_kernel(h->noise, h->xt, h->hy, in && in->obj_state ? 1 : 0, h->full);
+    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
+    if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+    rs = tg_readout_rollout(h, in, out, n_steps, hip_stream);           // warm-up
+    float ms = 0.f;
+    if (rs == TG_OK) {
+      (void)hipEventRecord(a, st);
+      rs = tg_readout_rollout(h, in, out, n_steps, hip_stream);
+      (void)hipEventRecord(b, st);
+      (void)hipEventSynchronize(b);
+      (void)hipEventElapsedTime(&ms, a, b);
+    }
+    if (rs == TG_OK && ms < bms) { bms = ms; best = c; }
+    if (rs == TG_OK) rs = tg_readout_set_state(h, saved, h->state_bytes, hip_stream);
+  }
+  (void)hipStreamSynchronize(st);
+  tg_status ps = plan_links(h, best);
+  if (ps == TG_OK && hipMemcpy(h->d_kp, &h->kp, sizeof(KParams), hipMemcpyHostToDevice) != hipSuccess) ps = TG_ERR_HIP;
+  if (ps == TG_OK) {
+    KernelFn kf = select_kernel(h->noise, h->xt, h->hy, 0, h->full);
+    KernelFn kf1 = select_kernel(h->noise, h->xt, h->hy, 1, h->full);
+    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
+    (void)hipFuncSetAttribute((const void*)kf1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
+  }
+  if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  (void)hipFree(saved);
+  if (rs != TG_OK) return rs;
+  if (ps != TG_OK) return fail(h, ps, "autotune: re-planning failed");
+  if (best_target) *best_target = best;
+  if (best_ms) *best_ms = bms;
+  return TG_OK;
 }
 
 tg_status tg_readout_state_size(const tg_readout* h, size_t* bytes) {

@@ -179,3 +179,57 @@ def test_c3_full_size_sampled(torch_cuda):
     info = parity.compare(sub, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
                           link_offset=sc.layout.link_offset)
     print("c3 full sampled", info)
+
+
+def test_graph_replays_equal_direct_launches(torch_cuda):
+    """Rollout in graph mode (recorded once, arguments updated per call) against plain launches,
+    over several calls with different step counters and eager work in between."""
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    sc = synth.make_scene("c2", num_envs=40, num_steps=6)
+    inp = synth.make_inputs(sc)
+    d = B.to_device(inp)
+    res = {}
+    for graph in (False, True):
+        ro = B.Readout(sc)
+        ro.set_graph(graph)
+        ro.alloc_outputs(3)
+        outs = []
+        for call in range(3):
+            d.step0 = 3 * call
+            ro.rollout(d, 3, s_in=3 * (call % 2))
+            torch.cuda.synchronize()
+            junk = torch.randn(1000, device="cuda").sum()      # eager work between replays
+            outs.append({k: v.clone() for k, v in ro.out.items()})
+            del junk
+        res[graph] = outs
+        ro.out = {}
+        ro.close()
+    for a, b in zip(res[False], res[True]):
+        for k in a:
+            assert torch.equal(a[k], b[k]), k
+
+
+def test_autotune_restores_state_and_keeps_parity(torch_cuda):
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    sc = synth.make_scene("c3", num_envs=48, num_steps=4)
+    inp = synth.make_inputs(sc)
+    d = B.to_device(inp)
+    ro = B.Readout(sc)
+    ro.alloc_outputs(4)
+    st0 = torch.empty(ro.state_size(), dtype=torch.uint8, device="cuda")
+    ro.get_state(st0)
+    best, ms = ro.autotune(d, 4)
+    assert best in (192, 256, 384, 512) and ms > 0
+    st1 = torch.empty_like(st0)
+    ro.get_state(st1)
+    assert torch.equal(st0, st1)
+    ro.rollout(d, 4)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in ro.out.items()}
+    ro.out = {}
+    ro.close()
+    ref = oracle_ref(sc, inp)
+    parity.compare(g, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
+                   link_offset=sc.layout.link_offset)
