@@ -68,6 +68,111 @@ def cpu_baseline(sc, inp, target_s=12.0):
             "sample": f"{n} of {sc.num_envs} envs x {T} taxels x {S} steps ({dt:.1f} s, FP32 oracle)"}
 
 
+def copy_calibration(nbytes: int) -> None:
+    """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
+    factor that turns those counters into bytes for the readout kernel."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": n * 4, "copies": 3}), flush=True)
+
+
+def angle_deg(a, b):
+    a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
+    return np.degrees(np.arctan2(np.linalg.norm(np.cross(a, b), axis=-1), np.sum(a * b, axis=-1)))
+
+
+def bench_c4(args) -> dict:
+    """Neural-SDF readout against the grid readout on the 256-object hand workload: trains the
+    per-object networks on the GPU, then times 16-step clean rollouts on both SDF backends and
+    reports the neural path's depth and normal error against the grid path."""
+    import torch
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+    t0 = time.perf_counter()
+    sc = synth.make_scene("c4", num_envs=args.envs)
+    sc.noise = synth.NoiseParams(enabled=False, seed=sc.noise.seed)
+    inp = synth.make_inputs(sc)
+    E, L, T, S = sc.num_envs, sc.layout.num_links, sc.layout.num_taxels, inp.link_state.shape[0]
+    n_obj = len(sc.grids)
+    pts = synth.nsdf_points(sc.grids, args.nsdf_samples, seed=sc.geom_seed + 7)
+    gen_s = time.perf_counter() - t0
+    ns = B.Nsdf(sc.grids)
+    rec = ns.targets(torch.from_numpy(pts).cuda())
+    del pts
+    P = torch.from_numpy(synth.nsdf_init(n_obj, sc.geom_seed + 8)).cuda()
+    m, v = torch.zeros_like(P), torch.zeros_like(P)
+    hp = B.train_params(lr=1e-3, batch=1 << 14, seed=sc.geom_seed + 9)
+    loss = torch.zeros((args.train_steps, n_obj), device="cuda")
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    ns.train(P, m, v, rec, 0, args.train_steps, hp, loss=loss)
+    b.record()
+    torch.cuda.synchronize()
+    train_ms = a.elapsed_time(b)
+    final_loss = loss[-50:].mean(0)
+    half = torch.tensor([0.5 * (g.n - 1) * float(g.spacing) for g in sc.grids], device="cuda")
+    loss_um = (final_loss * half * 1e6).cpu().numpy()
+    ns.close()
+    del rec
+    mask = B.TG_OUT_BITS | B.TG_OUT_DEPTH | B.TG_OUT_PROX | B.TG_OUT_FT | B.TG_OUT_NORMAL | B.TG_OUT_LINK_SUMS
+    d = B.to_device(inp)
+    res, outs = {}, {}
+    for name, kw in (("grid", {}), ("neural", {"nsdf_params": P, "nsdf_band": 1e-3})):
+        ro = B.Readout(sc, mask, **kw)
+        ro.alloc_outputs(S)
+        ro.rollout(d, S)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ro.rollout(d, S)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        res[name] = float(np.median(ts))
+        outs[name] = {k: ro.out[k] for k in ("depth", "normal")}
+        ro.out = {}
+        ro.close()
+    # error of the neural path against the grid path over taxels in contact on the grid path
+    dg, dn = outs["grid"]["depth"], outs["neural"]["depth"]
+    c = dg > 0
+    derr = (dn - dg).abs()[c].float().cpu().numpy()
+    ng = outs["grid"]["normal"].permute(0, 2, 3, 1)[c].cpu().numpy()
+    nn_ = outs["neural"]["normal"].permute(0, 2, 3, 1)[c].cpu().numpy()
+    both = (np.linalg.norm(nn_, axis=-1) > 0)
+    ang = angle_deg(nn_[both], ng[both])
+    readouts = E * T * S
+    return {
+        "metric": METRIC, "value": readouts / (res["neural"] * 1e-3), "unit": "taxel-readouts/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": res["neural"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16-mfma/f32", "data": "synthetic",
+        "config": {"workload": f"c4: {E} envs x {T} taxels ({L} links) x {S}-step clean rollout, {n_obj} objects, "
+                               "neural SDF (PE48-4x64 SiLU-1, BF16 MFMA) with grid fallback |phi|<1 mm",
+                   "envs": E, "taxels": T, "objects": n_obj, "steps_per_rollout": S},
+        "grid_path": {"ms_per_rollout": res["grid"], "readouts_per_s": readouts / (res["grid"] * 1e-3)},
+        "speedup_vs_grid": res["grid"] / res["neural"],
+        "depth_err_um": {"p50": float(np.quantile(derr, 0.5) * 1e6), "p99": float(np.quantile(derr, 0.99) * 1e6),
+                         "max": float(derr.max() * 1e6), "contacts": int(c.sum().item())},
+        "normal_err_deg": {"p50": float(np.quantile(ang, 0.5)), "p99": float(np.quantile(ang, 0.99)),
+                           "max": float(ang.max())},
+        "training": {"steps": args.train_steps, "batch_per_object": 1 << 14, "samples_per_object": args.nsdf_samples,
+                     "ms_total": train_ms, "ms_per_step": train_ms / args.train_steps,
+                     "final_l1_um_median": float(np.median(loss_um)), "final_l1_um_max": float(loss_um.max())},
+        "memory_MB": {"grids_fp32": n_obj * sc.grids[0].n ** 3 * 4 / 1e6,
+                      "network_bf16": n_obj * 15681 * 2 / 1e6,
+                      "network_images": n_obj * 65024 / 1e6},
+        "input_gen_s": gen_s,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,11 +183,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--workload", default="readout", choices=["readout", "c4"])
+    ap.add_argument("--train-steps", type=int, default=5000)
+    ap.add_argument("--nsdf-samples", type=int, default=1 << 17)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
               "(environments shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "c4":
+        print(json.dumps(bench_c4(args)), flush=True)
+        return
 
     import torch
     from paper_2606_22332_amd import binding as B

@@ -31,6 +31,7 @@ struct NLaunch {
   const KParams* kc;
   const NBox* boxes;
   const uint32_t* images;        // [n_obj][IMG_WORDS]
+  const uint16_t* silu;          // SiLU table (global copy; staged in LDS)
   const int32_t* order;          // [E] envs sorted by object id (invalid ids last)
   float band;
   int64_t step;                  // unused by the clean readout; kept for symmetry
@@ -92,9 +93,9 @@ __device__ __forceinline__ void pose_from_state(const float* st, int64_t col, in
   P.w[0] = st[10 * stride + col]; P.w[1] = st[11 * stride + col]; P.w[2] = st[12 * stride + col];
 }
 
-// LDS: image | link poses [L] | object pose | link sums [10][L]
+// LDS: image | SiLU table | link poses [L] | object pose | link sums [10][L]
 __host__ __device__ inline int neural_lds_bytes(int L) {
-  return nsdf::IMG_BYTES + (L + 1) * (int)sizeof(Pose) + 10 * L * 4 + 16;
+  return nsdf::IMG_BYTES + nsdf::SILU_BYTES + (L + 1) * (int)sizeof(Pose) + 10 * L * 4 + 16;
 }
 
 __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch q) {
@@ -104,7 +105,9 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
   const int E = p.E, L = p.L, T = p.T, W = p.W;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, s = lane & 15;
   uint32_t* img = (uint32_t*)smem;
-  Pose* lpose = (Pose*)(smem + IMG_BYTES);
+  uint16_t* tab = (uint16_t*)(smem + IMG_BYTES);
+  for (int i = tid; i < SILU_ENTRIES / 2; i += NEU_THREADS) ((uint32_t*)tab)[i] = ((const uint32_t*)q.silu)[i];
+  Pose* lpose = (Pose*)(smem + IMG_BYTES + SILU_BYTES);
   Pose* opose = lpose + L;
   float* sums = (float*)(opose + 1);
   const Img im = img_at(smem);
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
           uint32_t z[4][8];
           u32x4 pe[2];
           float a4[4][4];
-          const float out = forward_tile(im, lane, xh[0], xh[1], xh[2], z, pe, a4);
+          const float out = forward_tile(im, lane, xh[0], xh[1], xh[2], z, pe, a4, tab);
           const float phi_nn = bx.half * out;
           const bool need = valid && !far && ta.w > 0.f && !(fabsf(phi_nn) < q.band) && phi_nn < ta.w;
           float gx[3] = {0.f, 0.f, 0.f};

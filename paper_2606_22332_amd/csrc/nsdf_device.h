@@ -40,6 +40,13 @@ constexpr int W5_OFF = 15616, B5_OFF = 15680;
 constexpr int FWD_BYTES = 32768, BWD_BYTES = 30720, TAIL_FLOATS = 384;
 constexpr int IMG_BYTES = FWD_BYTES + BWD_BYTES + TAIL_FLOATS * 4;  // 65024
 constexpr int IMG_WORDS = IMG_BYTES / 4;
+// SiLU table: bf16(silu(z)) for every BF16 z with 2^-13 <= |z| < 2^7 (biased exponents
+// 114..133), indexed ((sign * 20 + exponent - 114) << 7) | mantissa.  Outside that range the
+// BF16 result has a closed form: z / 2 for smaller |z| (the z^2/4 term is below half an ulp),
+// z itself for z >= 128 and -0 for z <= -128 (the product underflows FP32).
+constexpr int SILU_E0 = 114, SILU_NE = 20;
+constexpr int SILU_ENTRIES = 2 * SILU_NE * 128;
+constexpr int SILU_BYTES = SILU_ENTRIES * 2;   // 10240
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef short short4v __attribute__((ext_vector_type(4)));
@@ -56,7 +63,12 @@ __device__ __forceinline__ f32x4 mfma16(u32x2 a, u32x2 b, f32x4 c) {
                                                    c, 0, 0, 0);
 }
 
-__device__ __forceinline__ uint32_t pack2(float lo, float hi) { return bf16_bits(lo) | (bf16_bits(hi) << 16); }
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// Two FP32 values rounded to BF16 (nearest even) and packed low, high: one v_cvt_pk_bf16_f32.
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){lo, hi}, bf16x2));
+}
 __device__ __forceinline__ float bf_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
@@ -189,6 +201,61 @@ __device__ __forceinline__ void activate(const f32x4 acc[4], uint32_t z[8], u32x
                      pack2(a[2 * kt + 1][0], a[2 * kt + 1][1]), pack2(a[2 * kt + 1][2], a[2 * kt + 1][3])};
 }
 
+// bf16(silu(z)) for the 16 BF16 pre-activations of a lane (4 packed words per pair of M-tiles,
+// z[8]), from the table in LDS.  The table index of bits b is (b & 0x7fff) - 114*128 plus 2560
+// for a negative sign; it is clamped into the table, and the rare values outside it (|z| < 2^-13
+// or |z| >= 128) are fixed up afterwards on a wave-uniform branch with their closed forms.
+__device__ __forceinline__ uint32_t silu_closed(uint32_t b) {
+  const uint32_t t = (b & 0x7fffu) - (uint32_t)(SILU_E0 << 7);
+  if ((int)t < 0) {   // |z| < 2^-13: z / 2
+    const float half = __uint_as_float(b << 16) * 0.5f;
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2){half, 0.f}, bf16x2)) & 0xffffu;
+  }
+  return (b >> 15) ? 0x8000u : b;   // |z| >= 128: z, or -0 below -128
+}
+__device__ __forceinline__ void silu_words(const uint32_t z[8], uint32_t out[8], const uint16_t* tab) {
+  uint32_t v[16];
+  bool any_out = false;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t b = (i & 1) ? (z[i >> 1] >> 16) : (z[i >> 1] & 0xffffu);
+    const uint32_t t = (b & 0x7fffu) - (uint32_t)(SILU_E0 << 7);
+    any_out |= t >= (uint32_t)(SILU_NE << 7);
+    const uint32_t idx = min(t, (uint32_t)(SILU_NE << 7) - 1u) + (b >> 15) * (uint32_t)(SILU_NE << 7);
+    v[i] = tab[idx];
+  }
+  if (__any(any_out)) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const uint32_t b = (i & 1) ? (z[i >> 1] >> 16) : (z[i >> 1] & 0xffffu);
+      const uint32_t t = (b & 0x7fffu) - (uint32_t)(SILU_E0 << 7);
+      if (t >= (uint32_t)(SILU_NE << 7)) v[i] = silu_closed(b);
+    }
+  }
+#pragma unroll
+  for (int w = 0; w < 8; ++w) out[w] = v[2 * w] | (v[2 * w + 1] << 16);
+}
+
+// Table path of a hidden layer: BF16 pre-activations (kept in z) and the next layer's BF16
+// input fragments, without transcendentals.  Word w of z holds items (2w, 2w+1) of M-tile w/2.
+__device__ __forceinline__ void activate_tab(const f32x4 acc[4], uint32_t z[8], u32x4 bout[2], const uint16_t* tab) {
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    z[2 * m] = pack2(acc[m][0], acc[m][1]);
+    z[2 * m + 1] = pack2(acc[m][2], acc[m][3]);
+  }
+  uint32_t a[8];
+  silu_words(z, a, tab);
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt) bout[kt] = u32x4{a[4 * kt], a[4 * kt + 1], a[4 * kt + 2], a[4 * kt + 3]};
+}
+__device__ __forceinline__ void act_frags_tab(const uint32_t z[8], u32x4 b[2], const uint16_t* tab) {
+  uint32_t a[8];
+  silu_words(z, a, tab);
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt) b[kt] = u32x4{a[4 * kt], a[4 * kt + 1], a[4 * kt + 2], a[4 * kt + 3]};
+}
+
 // Recompute a layer's BF16 input fragments from the stored BF16 pre-activations.
 __device__ __forceinline__ void act_frags(const uint32_t z[8], u32x4 b[2]) {
   float a[4][4];
@@ -214,7 +281,7 @@ __device__ __forceinline__ float group_sum(float v) {
 // Forward pass of one tile.  Returns the network output for sample (lane & 15) on every lane;
 // z receives the BF16 pre-activations of the four hidden layers, pe the input fragments.
 __device__ __forceinline__ float forward_tile(const Img& im, int lane, float x0, float x1, float x2,
-                                              uint32_t z[4][8], u32x4 pe[2], float a4[4][4]) {
+                                              uint32_t z[4][8], u32x4 pe[2], float a4[4][4], const uint16_t* tab) {
   const int g = lane >> 4;
   pe_frags(x0, x1, x2, g, pe);
   u32x4 b[2] = {pe[0], pe[1]};
@@ -224,7 +291,11 @@ __device__ __forceinline__ float forward_tile(const Img& im, int lane, float x0,
     __builtin_amdgcn_sched_barrier(0);   // keep each layer's fragment loads next to its MFMAs
     layer_fwd(im, l, lane, b, acc);
     u32x4 nb[2];
-    activate(acc, z[l], nb, a4);
+    if (l < 3) {
+      activate_tab(acc, z[l], nb, tab);   // layers 1-3 feed a BF16 GEMM: table SiLU
+    } else {
+      activate(acc, z[l], nb, a4);        // layer 4 feeds the FP32 output layer
+    }
     b[0] = nb[0];
     b[1] = nb[1];
   }
@@ -315,6 +386,23 @@ __device__ __forceinline__ void input_grad_tile(const Img& im, int lane, float x
   gx[0] = group_sum(p[0]);
   gx[1] = group_sum(p[1]);
   gx[2] = group_sum(p[2]);
+}
+
+// Host: the SiLU table, bf16(fp32(silu(z))) in FP64 with round to nearest even at both steps.
+inline void build_silu_table(uint16_t* t) {
+  for (int sgn = 0; sgn < 2; ++sgn)
+    for (int r = 0; r < SILU_NE; ++r)
+      for (int m = 0; m < 128; ++m) {
+        const uint32_t zb = ((uint32_t)sgn << 31) | ((uint32_t)(SILU_E0 + r) << 23) | ((uint32_t)m << 16);
+        float zf;
+        __builtin_memcpy(&zf, &zb, 4);
+        const double z = zf;
+        const float s = (float)(z / (1.0 + __builtin_exp(-z)));
+        uint32_t u;
+        __builtin_memcpy(&u, &s, 4);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        t[((sgn * SILU_NE + r) << 7) | m] = (uint16_t)(u >> 16);
+      }
 }
 
 }  // namespace nsdf

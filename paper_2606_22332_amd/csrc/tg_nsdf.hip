@@ -94,7 +94,8 @@ constexpr int SROW = 20;                    // staging row: 16 samples + pad (u1
 constexpr int STAGE_U16 = 64 * SROW;        // one [64 feature][16 sample] buffer
 constexpr int STAGE_BYTES = 4 * 4 * 2 * STAGE_U16 * 2;   // [wave][layer][dz | act]
 constexpr int RED_FLOATS = 68;              // dw5[64], db5, loss
-constexpr int LDS_FIT = IMG_BYTES + STAGE_BYTES + RED_FLOATS * 4;
+constexpr int LDS_TAB = IMG_BYTES + STAGE_BYTES + RED_FLOATS * 4;   // SiLU table
+constexpr int LDS_FIT = LDS_TAB + SILU_BYTES;
 
 __device__ __forceinline__ uint16_t* stage_buf(uint8_t* smem, int wave, int l, int which) {
   return (uint16_t*)(smem + IMG_BYTES) + ((wave * 4 + l) * 2 + which) * STAGE_U16;
@@ -133,12 +134,13 @@ __device__ __forceinline__ float bf_sum8(u32x4 v) {
 
 // Forward and backward of this wave's tile; stages dz and layer inputs of every layer.
 __device__ __forceinline__ void tile_backprop(const Img& im, uint8_t* smem, int wave, int lane, float4 rec, bool valid,
-                                              float inv_n, float dw5[4][4], float& db5, float& loss) {
+                                              float inv_n, float dw5[4][4], float& db5, float& loss,
+                                              const uint16_t* tab) {
   const int g = lane >> 4, s = lane & 15;
   uint32_t z[4][8];
   u32x4 pe[2];
   float a4[4][4];
-  const float out = forward_tile(im, lane, rec.x, rec.y, rec.z, z, pe, a4);
+  const float out = forward_tile(im, lane, rec.x, rec.y, rec.z, z, pe, a4, tab);
   const float r = out - rec.w;
   const float go = valid ? ((r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) * inv_n) : 0.f;
   if (g == 0 && valid) {
@@ -163,7 +165,7 @@ __device__ __forceinline__ void tile_backprop(const Img& im, uint8_t* smem, int 
       ain[0] = pe[0];
       ain[1] = pe[1];
     } else {
-      act_frags(z[l - 1], ain);
+      act_frags_tab(z[l - 1], ain, tab);
     }
     stage_frags(stage_buf(smem, wave, l, 0), db, g, s, false);
     stage_frags(stage_buf(smem, wave, l, 1), ain, g, s, l == 0);
@@ -224,6 +226,7 @@ struct FitArgs {
   int n_steps, n_obj, batch;
   float lr, b1, b2, eps;
   uint32_t key0, key1;
+  const uint16_t* silu;     // SiLU table (global copy; staged in LDS)
 };
 
 }  // namespace
@@ -238,6 +241,8 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
   float* Po = a.P + (size_t)o * NPARAM;
   const float4* So = a.samples + (size_t)o * a.n;
   for (int w = tid; w < IMG_WORDS; w += NT) ((uint32_t*)smem)[w] = image_word(Po, w);
+  uint16_t* tab = (uint16_t*)(smem + LDS_TAB);
+  for (int i = tid; i < SILU_ENTRIES / 2; i += NT) ((uint32_t*)tab)[i] = ((const uint32_t*)a.silu)[i];
   const Img im = img_at(smem);
   const int64_t per_step = TRAIN ? a.batch : a.n;
   const float inv_n = 1.0f / (float)per_step;
@@ -273,7 +278,7 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
         valid = j < a.n;
       }
       const float4 rec = valid ? So[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-      tile_backprop(im, smem, wave, lane, rec, valid, inv_n, dw5, db5, lossp);
+      tile_backprop(im, smem, wave, lane, rec, valid, inv_n, dw5, db5, lossp, tab);
       __syncthreads();
       owner_wgrad(smem, L, lane, acc, dbp);
       __syncthreads();
@@ -384,7 +389,7 @@ constexpr int QUERY_TILES_PER_WAVE = 8;
 __global__ __launch_bounds__(NT) void nsdf_query_kernel(const uint32_t* __restrict__ images,
                                                         const int64_t* __restrict__ offsets,
                                                         const float* __restrict__ xhat, float* __restrict__ out,
-                                                        float* __restrict__ grad) {
+                                                        float* __restrict__ grad, const uint16_t* __restrict__ silu) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int o = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t beg = offsets[o], end = offsets[o + 1];
@@ -393,6 +398,8 @@ __global__ __launch_bounds__(NT) void nsdf_query_kernel(const uint32_t* __restri
   uint32_t* img = (uint32_t*)smem;
   const uint32_t* src = images + (size_t)o * IMG_WORDS;
   for (int w = tid; w < IMG_WORDS; w += NT) img[w] = src[w];
+  uint16_t* tab = (uint16_t*)(smem + IMG_BYTES);
+  for (int i = tid; i < SILU_ENTRIES / 2; i += NT) ((uint32_t*)tab)[i] = ((const uint32_t*)silu)[i];
   __syncthreads();
   const Img im = img_at(smem);
   for (int tt = 0; tt < QUERY_TILES_PER_WAVE; ++tt) {
@@ -408,7 +415,7 @@ __global__ __launch_bounds__(NT) void nsdf_query_kernel(const uint32_t* __restri
     uint32_t z[4][8];
     u32x4 pe[2];
     float a4[4][4];
-    const float y = forward_tile(im, lane, x0, x1, x2, z, pe, a4);
+    const float y = forward_tile(im, lane, x0, x1, x2, z, pe, a4, tab);
     float gx[3] = {0.f, 0.f, 0.f};
     if (grad) input_grad_tile(im, lane, x0, x1, x2, z, gx);
     if (valid && lane < 16) {
@@ -430,6 +437,7 @@ struct tg_nsdf {
   BoxDesc* d_boxes = nullptr;
   float* d_vals = nullptr;
   uint32_t* d_img = nullptr;
+  uint16_t* d_silu = nullptr;
   std::string err;
 };
 
@@ -483,11 +491,15 @@ tg_status tg_nsdf_create(const tg_nsdf_config* cfg, tg_nsdf** out) {
   h->n_obj = cfg->num_objects;
   if (hipMalloc(&h->d_boxes, sizeof(BoxDesc) * boxes.size()) != hipSuccess ||
       hipMalloc(&h->d_vals, sizeof(float) * total) != hipSuccess ||
-      hipMalloc(&h->d_img, (size_t)IMG_BYTES * h->n_obj) != hipSuccess) {
+      hipMalloc(&h->d_img, (size_t)IMG_BYTES * h->n_obj) != hipSuccess ||
+      hipMalloc(&h->d_silu, SILU_BYTES) != hipSuccess) {
     tg_nsdf_destroy(h);
     return nfail(nullptr, TG_ERR_OUT_OF_MEMORY, "device allocation failed");
   }
+  std::vector<uint16_t> silu(SILU_ENTRIES);
+  build_silu_table(silu.data());
   hipError_t e = hipMemcpy(h->d_boxes, boxes.data(), sizeof(BoxDesc) * boxes.size(), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(h->d_silu, silu.data(), SILU_BYTES, hipMemcpyHostToDevice);
   for (int o = 0; o < cfg->num_objects && e == hipSuccess; ++o) {
     const tg_sdf_grid& g = cfg->grids[o];
     e = hipMemcpy(h->d_vals + boxes[o].grid.offset, g.values, sizeof(float) * (size_t)g.n * g.n * g.n,
@@ -506,6 +518,7 @@ tg_status tg_nsdf_destroy(tg_nsdf* h) {
   if (h->d_boxes) (void)hipFree(h->d_boxes);
   if (h->d_vals) (void)hipFree(h->d_vals);
   if (h->d_img) (void)hipFree(h->d_img);
+  if (h->d_silu) (void)hipFree(h->d_silu);
   delete h;
   return TG_OK;
 }
@@ -538,6 +551,7 @@ tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, in
   a.grad = grad;
   a.loss = loss;
   a.n_obj = h->n_obj;
+  a.silu = h->d_silu;
   hipLaunchKernelGGL(nsdf_fit_kernel<0>, dim3(h->n_obj), dim3(NT), LDS_FIT, (hipStream_t)stream, a);
   e = hipGetLastError();
   return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
@@ -581,6 +595,7 @@ tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const flo
   a.eps = hp->eps;
   a.key0 = (uint32_t)hp->seed;
   a.key1 = (uint32_t)(hp->seed >> 32);
+  a.silu = h->d_silu;
   hipLaunchKernelGGL(nsdf_fit_kernel<1>, dim3(h->n_obj), dim3(NT), LDS_FIT, (hipStream_t)stream, a);
   e = hipGetLastError();
   return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
@@ -597,7 +612,8 @@ tg_status tg_nsdf_query(tg_nsdf* h, const float* params, const int64_t* offsets,
   if (max_count > 0) {
     const int64_t per_block = 4 * 16 * QUERY_TILES_PER_WAVE;
     const dim3 grid((unsigned)((max_count + per_block - 1) / per_block), (unsigned)h->n_obj);
-    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES, s, h->d_img, offsets, xhat, out, grad);
+    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES + SILU_BYTES, s, h->d_img, offsets, xhat, out, grad,
+                       h->d_silu);
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));

@@ -74,6 +74,7 @@ struct tg_readout {
   NBox* d_boxes = nullptr;
   uint32_t* d_img = nullptr;
   int32_t* d_order = nullptr;
+  uint16_t* d_silu = nullptr;
   size_t neural_lds = 0;
   // launch graph of the rollout (recorded on a private stream, replayed on the caller's)
   int graph_on = 1;
@@ -516,6 +517,10 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     e = dalloc(h, &h->d_boxes, NO);
     if (e == hipSuccess) e = dalloc(h, &h->d_img, (size_t)NO * nsdf::IMG_WORDS);
     if (e == hipSuccess) e = dalloc(h, &h->d_order, E);
+    if (e == hipSuccess) e = dalloc(h, &h->d_silu, nsdf::SILU_ENTRIES);
+    std::vector<uint16_t> silu(nsdf::SILU_ENTRIES);
+    nsdf::build_silu_table(silu.data());
+    if (e == hipSuccess) e = hipMemcpy(h->d_silu, silu.data(), nsdf::SILU_BYTES, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(h->d_boxes, bx.data(), NO * sizeof(NBox), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = nsdf_pack_images(cfg->nsdf_params, NO, h->d_img, nullptr);
     h->neural_lds = (size_t)neural_lds_bytes(L);
@@ -689,6 +694,7 @@ static tg_status launch_rollout(tg_readout* h, const tg_step_inputs* in, const t
       q.kc = h->d_kp;
       q.boxes = h->d_boxes;
       q.images = h->d_img;
+      q.silu = h->d_silu;
       q.order = h->d_order;
       q.band = h->cfg.nsdf_band;
       q.step = in->step + s;
