@@ -45,10 +45,20 @@ __device__ __forceinline__ Pose pose_from13(const float* v) {
   return P;
 }
 
+// Store through a uniform base and a per-lane 32-bit byte offset (scalar-base addressing).
+__device__ __forceinline__ void store_at(float* base, uint32_t off4, float v) { *(float*)((char*)base + off4) = v; }
+
+// Two FP32 values rounded to BF16 (nearest even), packed low, high (one v_cvt_pk_bf16_f32).
+__device__ __forceinline__ uint32_t bf16_pack2(float lo, float hi) {
+  typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){lo, hi}, bf2));
+}
+
 // Sum of S[ch][el*n + k], k < n, for (el, ch) items handled by groups of 8 lanes; writes the
 // 11 link observations (f, tau, count, agg_bool, agg_force) of one step to `out`.
-template <class KP>
-__device__ __forceinline__ void link_reduce(KP& p, const LinkInfo& li, const float* S, int nthr, int e0, int l,
+template <class KP, class LI>
+__device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* S, int nthr, int e0, int l,
                                             float* out) {
   const int n = li.n, envs = li.envs;
   const int items = envs * 10;
@@ -83,8 +93,8 @@ __device__ __forceinline__ void link_reduce(KP& p, const LinkInfo& li, const flo
 }
 
 // Merge the LDS bit windows of this block's envs into the global [E][W] words of one step.
-template <class KP>
-__device__ __forceinline__ void store_bits(KP& p, const LinkInfo& li, const unsigned* win, int e0,
+template <class KP, class LI>
+__device__ __forceinline__ void store_bits(KP& p, LI& li, const unsigned* win, int e0,
                                            unsigned long long* out_step) {
   const int nw = li.nwin;
   const int wstart = li.off >> 6;
@@ -113,13 +123,18 @@ __device__ __forceinline__ void store_bits(KP& p, const LinkInfo& li, const unsi
 // quantisation, per-probe gain, probe-radius noise, normal / surface-distance outputs) so that
 // the common path fits in 128 VGPRs (4 waves per SIMD) without spilling.
 template <int NOISE, int XT, int HY, int OBJ, int FULL>
-__global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
-  // The handle's constants are read through a constant-memory pointer that is made opaque at the
-  // top of every step, so the compiler reloads them (scalar loads) within the step instead of
+__global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
+  // The handle's constants and this launch's arguments are read through constant-memory pointers
+  // (the parameter block and the kernel-argument segment) that are made opaque at the top of
+  // every step, so the compiler reloads them with scalar loads where they are used instead of
   // keeping all of them live in SGPRs across the whole step loop.
+  (void)qarg;
+  typedef const __attribute__((address_space(4))) KLaunch* QPtr;
+  QPtr qp = (QPtr)__builtin_amdgcn_kernarg_segment_ptr();
   typedef const __attribute__((address_space(4))) KParams* KcPtr;   // constant memory: scalar loads
-  KcPtr kc = (KcPtr)q.kc;
-#define TG_REFRESH() asm volatile("" : "+s"(kc))
+  KcPtr kc = (KcPtr)qp->kc;
+#define q (*qp)
+#define TG_REFRESH() asm volatile("" : "+s"(kc), "+s"(qp))
 #define TG_REFRESH_PHASE() do {} while (0)
 #define p (*kc)
   TG_REFRESH();
@@ -130,7 +145,9 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
   if (item_id >= p.n_items) return;
   const int2 item = p.items[item_id];
   const int l = item.x, e0 = item.y;
-  const LinkInfo li = p.links[l];   // (copied: plain struct in registers)
+  typedef const __attribute__((address_space(4))) LinkInfo* LiPtr;
+  LiPtr lip = (LiPtr)(p.links + l);    // read where used; refreshed with the other pointers
+#define li (*lip)
   const int n = li.n, envs = li.envs;
   const int tid = threadIdx.x;
   const int nthr = blockDim.x;
@@ -157,6 +174,9 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
   const int64_t ET = (int64_t)p.E * p.T;
   const int64_t EL = (int64_t)p.E * p.L;
   const int64_t kk = (int64_t)e * p.T + j;
+  // byte offset of (e, j) in an [E][T] plane: fits 32 bits (checked at create), so every output
+  // store is a uniform per-step base plus this fixed lane offset
+  const uint32_t off4 = (uint32_t)kk * 4u;
 
   for (int i = tid; i < n; i += nthr) {
     TX[2 * i] = p.taxA[li.off + i];
@@ -205,6 +225,7 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
 
   for (int s = 0; s < q.n_steps; ++s) {
     TG_REFRESH();
+    asm volatile("" : "+s"(lip));
     const int64_t t = q.step0 + s;
     const int par = s & 1;
     Pose* lp = lpose + par * envs;
@@ -245,19 +266,21 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
     const bool bit = o.depth > p.eta_on;
     const int wbit = (li.off & 63) + k;   // bit position inside this env's window
     if (act) {
-      const int64_t ok = (int64_t)s * ET + kk;
-      if (q.depth) q.depth[ok] = o.depth;
-      if (q.prox) q.prox[ok] = o.prox;
-      if (FULL && q.surfdist) q.surfdist[ok] = o.surf;
+      if (q.depth) store_at(q.depth + (int64_t)s * ET, off4, o.depth);
+      if (q.prox) store_at(q.prox + (int64_t)s * ET, off4, o.prox);
+      if (FULL && q.surfdist) store_at(q.surfdist + (int64_t)s * ET, off4, o.surf);
       if (q.ft) {
-        float* f = q.ft + (int64_t)s * 6 * ET + kk;
+        float* f = q.ft + (int64_t)s * 6 * ET;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) { f[c * ET] = o.f[c]; f[(c + 3) * ET] = o.tau[c]; }
+        for (int c = 0; c < 3; ++c) {
+          store_at(f + c * ET, off4, o.f[c]);
+          store_at(f + (c + 3) * ET, off4, o.tau[c]);
+        }
       }
       if (FULL && q.normal) {
-        float* nm = q.normal + (int64_t)s * 3 * ET + kk;
+        float* nm = q.normal + (int64_t)s * 3 * ET;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) nm[c * ET] = o.mb[c];
+        for (int c = 0; c < 3; ++c) store_at(nm + c * ET, off4, o.mb[c]);
       }
       if (bit) atomicOr(&bw[el * li.nwin * 2 + (wbit >> 5)], 1u << (wbit & 31));
     }
@@ -278,7 +301,11 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
     if (NOISE && XT == 2 && act) {
       uint16_t* bt = (uint16_t*)(smem + Ld.bt);
 #pragma unroll
-      for (int c = 0; c < 6; ++c) bt[(6 * el + c) * li.kp + k] = (uint16_t)bf16_bits(z[c]);
+      for (int c = 0; c < 6; c += 2) {
+        const uint32_t w = bf16_pack2(z[c], z[c + 1]);
+        bt[(6 * el + c) * li.kp + k] = (uint16_t)(w & 0xffffu);
+        bt[(6 * el + c + 1) * li.kp + k] = (uint16_t)(w >> 16);
+      }
     }
     if (!NOISE && pre && pf_off != -1) RAW[(par ^ 1) * nraw + tid] = rv;   // the other parity is free
     __syncthreads();   // B2: clean bits, sums, crosstalk operands
@@ -404,9 +431,9 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
         fo[c] = v;
       }
       if (act && q.ft_noisy) {
-        float* f = q.ft_noisy + (int64_t)s * 6 * ET + kk;
+        float* f = q.ft_noisy + (int64_t)s * 6 * ET;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) f[c * ET] = fo[c];
+        for (int c = 0; c < 6; ++c) store_at(f + c * ET, off4, fo[c]);
       }
       float dd = o.depth;
       if (FULL && p.has_radius) {
@@ -454,6 +481,8 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch q) {
 }
 
 #undef p
+#undef q
+#undef li
 #undef TG_REFRESH
 #undef TG_REFRESH_PHASE
 }  // namespace tg

@@ -137,14 +137,17 @@ __device__ __forceinline__ void grid_lookup(const GridDesc& g, const float* grid
     ii[i] = k;
     h.t[i] = uc[i] - (float)k;
   }
-  const float* G = grid_vals + g.offset;
+  // 32-bit byte offsets from the (uniform) base of all grids: the loads use a scalar base
   const int N = g.n;
-  const uint32_t base = ((uint32_t)ii[2] * (uint32_t)N + (uint32_t)ii[1]) * (uint32_t)N + (uint32_t)ii[0];
+  const uint32_t base = (uint32_t)g.offset + ((uint32_t)ii[2] * (uint32_t)N + (uint32_t)ii[1]) * (uint32_t)N +
+                        (uint32_t)ii[0];
   const uint32_t sy = (uint32_t)N, sz = (uint32_t)N * (uint32_t)N;
-  h.c000 = G[base]; h.c100 = G[base + 1];
-  h.c010 = G[base + sy]; h.c110 = G[base + sy + 1];
-  h.c001 = G[base + sz]; h.c101 = G[base + sz + 1];
-  h.c011 = G[base + sz + sy]; h.c111 = G[base + sz + sy + 1];
+  const char* Gb = (const char*)grid_vals;
+  const uint32_t o0 = base * 4u, oy = (base + sy) * 4u, oz = (base + sz) * 4u, oyz = (base + sz + sy) * 4u;
+  h.c000 = *(const float*)(Gb + o0); h.c100 = *(const float*)(Gb + o0 + 4u);
+  h.c010 = *(const float*)(Gb + oy); h.c110 = *(const float*)(Gb + oy + 4u);
+  h.c001 = *(const float*)(Gb + oz); h.c101 = *(const float*)(Gb + oz + 4u);
+  h.c011 = *(const float*)(Gb + oyz); h.c111 = *(const float*)(Gb + oyz + 4u);
   const float* t = h.t;
   const float l00 = lerpf(t[0], h.c000, h.c100), l10 = lerpf(t[0], h.c010, h.c110);
   const float l01 = lerpf(t[0], h.c001, h.c101), l11 = lerpf(t[0], h.c011, h.c111);

@@ -280,6 +280,8 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
   }
   const uint32_t om = cfg->output_mask;
   if ((om & TG_OUT_NOISY) && !noise) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "noisy outputs need noise");
+  if ((int64_t)E * T * 4 > (int64_t)0xffffffffLL)
+    return fail(nullptr, TG_ERR_UNSUPPORTED, "num_envs * num_taxels * 4 must fit 32 bits (shard the envs)");
   if (cfg->sdf_mode != 0 && cfg->sdf_mode != 1) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "sdf_mode must be 0 or 1");
   if (cfg->sdf_mode == 1) {
     if (noise) return fail(nullptr, TG_ERR_UNSUPPORTED, "the neural SDF backend computes the clean readout only");
@@ -348,6 +350,10 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
   h->hy = noise ? nz.hyst_mode : 0;
   int64_t total_vals = 0;
   for (int g = 0; g < NO; ++g) total_vals += (int64_t)cfg->grids[g].n * cfg->grids[g].n * cfg->grids[g].n;
+  if (total_vals * 4 > (int64_t)0xffffffffLL) {   // grid corners are addressed with 32-bit byte offsets
+    delete h;
+    return fail(nullptr, TG_ERR_UNSUPPORTED, "grid values exceed 4 GiB");
+  }
 
   // host staging
   std::vector<float4> tA(T), tB(T);
