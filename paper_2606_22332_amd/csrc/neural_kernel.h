@@ -98,10 +98,19 @@ __host__ __device__ inline int neural_lds_bytes(int L) {
   return nsdf::IMG_BYTES + nsdf::SILU_BYTES + (L + 1) * (int)sizeof(Pose) + 10 * L * 4 + 16;
 }
 
-__global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch q) {
+__global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch qarg) {
   using namespace nsdf;
   extern __shared__ __align__(16) uint8_t smem[];
-  const KParams& p = *q.kc;
+  // launch arguments and handle constants through constant-address pointers refreshed per env:
+  // scalar reloads instead of SGPRs pinned for the whole launch
+  (void)qarg;
+  typedef const __attribute__((address_space(4))) NLaunch* QPtr;
+  typedef const __attribute__((address_space(4))) KParams* KcPtr;
+  QPtr qp = (QPtr)__builtin_amdgcn_kernarg_segment_ptr();
+  KcPtr kc = (KcPtr)qp->kc;
+#define q (*qp)
+#define p (*kc)
+#define NEU_REFRESH() asm volatile("" : "+s"(kc), "+s"(qp))
   const int E = p.E, L = p.L, T = p.T, W = p.W;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, s = lane & 15;
   uint32_t* img = (uint32_t*)smem;
@@ -115,6 +124,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
   int loaded = -1;
 #pragma unroll 1
   for (int k = 0; k < NEU_ENVS; ++k) {
+    NEU_REFRESH();
     const int idx = blockIdx.x * NEU_ENVS + k;
     if (idx >= E) break;                                   // uniform
     const int e = q.order[idx];
@@ -267,5 +277,9 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
     }
   }
 }
+
+#undef q
+#undef p
+#undef NEU_REFRESH
 
 }  // namespace tg
