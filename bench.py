@@ -82,6 +82,46 @@ def copy_calibration(nbytes: int) -> None:
     print(json.dumps({"copy_bytes": n * 4, "copies": 3}), flush=True)
 
 
+# Sources that define the readout kernel and its launch plan: HBM counters taken on another
+# version of them no longer describe the kernel that runs.
+KERNEL_SOURCES = ["readout_device.h", "readout_kernel.h", "link_kernel.h", "xtalk_dense.h", "tg_readout.hip"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "tg_link_kernel_c3_hbm_counters.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2606_22332_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload_key: str):
+    """HBM bytes per launch of the readout kernel from the committed counter summary: FETCH_SIZE
+    and WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads for a plain copy
+    of known size.  None when there is no summary for this workload or the kernel sources have
+    changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    kv = {}
+    with open(TRAFFIC_PROFILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(("#", "|", " ")):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        if kv["source_sha256"] != kernel_source_hash() or kv["workload_key"] != workload_key:
+            return None
+        cb = float(kv["copy_bytes"])
+        f_fetch = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
+        f_write = cb / (float(kv["copy_write_kib"]) * 1024.0)
+        return (float(kv["fetch_kib_per_dispatch"]) * 1024.0 * f_fetch
+                + float(kv["write_kib_per_dispatch"]) * 1024.0 * f_write)
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+
+
 def angle_deg(a, b):
     a = np.asarray(a, np.float64); b = np.asarray(b, np.float64)
     return np.degrees(np.arctan2(np.linalg.norm(np.cross(a, b), axis=-1), np.sum(a * b, axis=-1)))
@@ -249,6 +289,7 @@ def main():
     nbytes, _ = algorithmic_bytes(E, L, T, S, len(sc.grids), sc.grids[0].n, sc.noise.enabled, True)
     achieved = nbytes / (ms * 1e-3) / 1e9
     eb, threads = ro.launch_shape()
+    wkey = f"{sc.name}:E{E}:T{T}:S{S}:target{eb}:threads{threads}"
     rec = {
         "metric": METRIC, "value": value, "unit": "taxel-readouts/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
@@ -261,10 +302,11 @@ def main():
                    "readouts_per_block_target": eb, "threads_per_block": threads,
                    "autotuned": tuned is not None, "graph": not args.no_graph},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(wkey),
                      "kernel": "tg_link_kernel", "algorithmic_bytes_per_launch": nbytes,
                      "bytes_per_readout": nbytes / readouts, "kernel_ms_mean": ms,
-                     "kernel_ms_min": float(np.min(kernel_ms))},
+                     "kernel_ms_min": float(np.min(kernel_ms)), "workload_key": wkey,
+                     "kernel_source_sha256": kernel_source_hash()},
         "input_gen_s": gen_s,
     }
     if not args.no_cpu_baseline:

@@ -5,6 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -800,6 +802,8 @@ tg_status tg_readout_autotune(tg_readout* h, const tg_step_inputs* in, const tg_
       (void)hipEventSynchronize(b);
       (void)hipEventElapsedTime(&ms, a, b);
     }
+    if (rs == TG_OK && std::getenv("TG_AUTOTUNE_VERBOSE"))
+      std::fprintf(stderr, "tg_readout_autotune: %d readouts per workgroup, %d threads: %.3f ms\n", c, h->threads, ms);
     if (rs == TG_OK && ms < bms) { bms = ms; best = c; }
     if (rs == TG_OK) rs = tg_readout_set_state(h, saved, h->state_bytes, hip_stream);
   }

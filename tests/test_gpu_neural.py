@@ -79,10 +79,23 @@ def test_band_everywhere_equals_grid_path(torch_cuda, moving):
     parity.compare(g, ref, sc.layout.num_taxels, noisy=False, link_offset=sc.layout.link_offset)
 
 
-def neural_tolerances(g, r, k_n, c_n, taxel_pos):
+def max_spin(inp):
+    """Bound on |omega_obj - omega_link| over the inputs (rad/s)."""
+    w = np.linalg.norm(inp.link_state[:, 10:13, :].astype(np.float64), axis=1).max()
+    if inp.obj_state is not None:
+        w += np.linalg.norm(inp.obj_state[:, 10:13, :].astype(np.float64), axis=1).max()
+    return float(w)
+
+
+def neural_tolerances(g, r, force, taxel_pos, wmax):
     """Bars of the network path: phi p99.9 <= 20 um (max 200 um); normals p99 <= 0.1 deg (max 2);
     depth follows phi; bits agree wherever the oracle depth is farther from eta_on than the
-    observed phi difference; F/T within what the observed depth and normal differences allow."""
+    observed phi difference; F/T within what the observed depth and normal differences allow.
+    The torsional term k_w (dw . m) m of the torque does not scale with depth (App. A, kinematic
+    taxel): where the two sides disagree on d > 0 it appears on one side only (at most
+    k_w |dw|), and where both are in contact it turns with the normal (at most 2 k_w |dw| per
+    radian of normal difference)."""
+    k_n, c_n, k_w = force.k_n, force.c_n, force.k_w
     act = r["surfdist"] < 1e30
     dphi = np.abs(g["surfdist"].astype(np.float64) - r["surfdist"])
     dphi[~act] = 0.0
@@ -110,7 +123,8 @@ def neural_tolerances(g, r, k_n, c_n, taxel_pos):
     xmax = float(np.abs(taxel_pos).max()) + 0.05
     rad = np.radians(ang) * 1.5 + 1e-5
     tol_f = (k_n + c_n) * 1.5 * dd + rad * np.abs(rf).max(-1) + 1e-5 * np.abs(rf).max(-1) + 1e-6
-    tol_t = xmax * tol_f + rad * np.abs(rt).max(-1) + 1e-6
+    onset = (g["depth"] > 0) != (r["depth"] > 0)
+    tol_t = xmax * tol_f + rad * (np.abs(rt).max(-1) + 2.0 * k_w * wmax) + onset * (1.01 * k_w * wmax) + 1e-6
     assert np.all(np.abs(gf - rf).max(-1) <= tol_f), float((np.abs(gf - rf).max(-1) / tol_f).max())
     assert np.all(np.abs(gt - rt).max(-1) <= tol_t), float((np.abs(gt - rt).max(-1) / tol_t).max())
     return info
@@ -123,7 +137,7 @@ def test_network_everywhere_matches_neural_oracle(torch_cuda, cfg):
     P = params_for(sc, seed=7)
     g = run_neural(sc, inp, P, band=0.0)
     r = oracle.run_readout(sc, inp, precision="f32", nsdf_params=P, nsdf_band=0.0)
-    info = neural_tolerances(g, r, sc.force.k_n, sc.force.c_n, sc.layout.pos)
+    info = neural_tolerances(g, r, sc.force, sc.layout.pos, max_spin(inp))
     assert info["contacts"] > 0
     print(info)
 

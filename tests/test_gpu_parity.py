@@ -171,10 +171,12 @@ def test_c3_full_size_sampled(torch_cuda):
     """The benchmark's launch: 20480 envs x 1024 taxels x 64 steps in one rollout; sampled envs
     are recomputed by the oracle over every step."""
     torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
     sc = synth.make_scene("c3")
     inp = synth.make_inputs(sc)
     envs = np.array([0, 1, 4095, 10000, 20478, 20479])
-    sub = run_gpu(sc, inp, envs=envs)
+    mask = B.TG_OUT_BITS | B.TG_OUT_DEPTH | B.TG_OUT_PROX | B.TG_OUT_FT | B.TG_OUT_LINK_SUMS | B.TG_OUT_NOISY
+    sub = run_gpu(sc, inp, mask=mask, envs=envs)       # the output set and kernel the benchmark times
     ref = oracle.run_readout(sc, synth.subset_envs(inp, envs, sc.layout.num_links), envs=envs, precision="f32")
     info = parity.compare(sub, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
                           link_offset=sc.layout.link_offset)
