@@ -222,6 +222,8 @@ def main():
     ap.add_argument("--envs", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--readouts-per-block", type=int, default=0,
+                    help="fix the work plan instead of autotuning (the profiles pin the autotuner's choice)")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--workload", default="readout", choices=["readout", "c4"])
     ap.add_argument("--train-steps", type=int, default=5000)
@@ -260,7 +262,9 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     tuned = None
-    if not args.no_autotune:
+    if args.readouts_per_block:
+        ro.set_work_plan(args.readouts_per_block)
+    elif not args.no_autotune:
         tuned = ro.autotune(dinp, S)
 
     # rollouts continue one another (the step counter advances by S each time), as in a long

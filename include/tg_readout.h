@@ -177,9 +177,11 @@ typedef struct {
   float* ft;                     /* [6][E][T] fx fy fz tx ty tz, link frame                */
   float* ft_noisy;               /* [6][E][T]                                              */
   float* normal;                 /* [3][E][T] link-frame contact normal (0 if no contact)  */
-  float* link_sums;              /* [11][E][L] sum f(3), sum tau(3), count, agg_bool,
-                                    agg_force = 1e4 (sum d n_z, sum d n_y, sum d n_x)       */
-  float* link_sums_noisy;        /* [11][E][L] same on the noisy channel                   */
+  float* link_sums;              /* [11][L][E] sum f(3), sum tau(3), count, agg_bool,
+                                    agg_force = 1e4 (sum d n_z, sum d n_y, sum d n_x);
+                                    env-innermost, so a workgroup's envs of one link are
+                                    contiguous (App. B.2 per-link observations)            */
+  float* link_sums_noisy;        /* [11][L][E] same on the noisy channel                   */
   float* temperature;            /* [E][T] after the step: temperature of the top-layer voxel
                                     under each taxel of a thermal link, 0 elsewhere         */
 } tg_step_outputs;
@@ -227,6 +229,13 @@ tg_status tg_readout_set_graph(tg_readout* h, int32_t enable);
  * neural backend has no plan to tune (best_target = 0). */
 tg_status tg_readout_autotune(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, int32_t n_steps,
                               void* hip_stream, int32_t* best_target, float* best_ms);
+
+/* Fix the readout kernel's work plan without timing: about `readouts_per_workgroup` readouts
+ * (64..1024) per workgroup, as the autotuner would set it.  Synchronises the device.  Returns
+ * TG_ERR_INVALID_ARGUMENT for a size outside 64..1024 or a plan whose LDS exceeds the 160 KiB of
+ * a gfx950 CU, TG_ERR_UNSUPPORTED for one that needs more than 512 threads per workgroup; the
+ * previous plan is then kept.  The neural backend has no plan (no-op). */
+tg_status tg_readout_set_work_plan(tg_readout* h, int32_t readouts_per_workgroup);
 
 /* Release the handle and its device memory (synchronises the device). NULL is accepted. */
 tg_status tg_readout_destroy(tg_readout* h);

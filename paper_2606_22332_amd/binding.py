@@ -92,6 +92,7 @@ def load() -> C.CDLL:
         "tg_readout_launch_shape": ([P, P, P], C.c_int),
         "tg_readout_set_graph": ([P, C.c_int32], C.c_int),
         "tg_readout_autotune": ([P, P, P, C.c_int32, P, P, P], C.c_int),
+        "tg_readout_set_work_plan": ([P, C.c_int32], C.c_int),
         "tg_readout_destroy": ([P], C.c_int),
         "tg_readout_last_error": ([P], C.c_char_p),
         "tg_status_string": ([C.c_int], C.c_char_p),
@@ -254,9 +255,10 @@ class Readout:
         if m & TG_OUT_NORMAL:
             o["normal"] = torch.zeros((steps, 3, E, T), **f32)
         if m & TG_OUT_LINK_SUMS:
-            o["link_sums"] = torch.zeros((steps, 11, E, L), **f32)
+            # the library writes [S][11][L][E]; exposed as a [S][11][E][L] view
+            o["link_sums"] = torch.zeros((steps, 11, L, E), **f32).permute(0, 1, 3, 2)
             if m & TG_OUT_NOISY:
-                o["link_sums_noisy"] = torch.zeros((steps, 11, E, L), **f32)
+                o["link_sums_noisy"] = torch.zeros((steps, 11, L, E), **f32).permute(0, 1, 3, 2)
         if m & TG_OUT_TEMP:
             o["temperature"] = torch.zeros((steps, E, T), **f32)
         self.out = o
@@ -312,6 +314,10 @@ class Readout:
 
     def set_graph(self, enable: bool):
         _check(self.lib, self.h, self.lib.tg_readout_set_graph(self.h, int(bool(enable))), "set_graph")
+
+    def set_work_plan(self, readouts_per_workgroup: int):
+        _check(self.lib, self.h, self.lib.tg_readout_set_work_plan(self.h, int(readouts_per_workgroup)),
+               "set_work_plan")
 
     def autotune(self, dinp: DeviceInputs, n_steps: Optional[int] = None, stream=None):
         """Time the candidate work plans on these inputs (outputs are overwritten, state restored);

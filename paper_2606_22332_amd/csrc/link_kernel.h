@@ -56,7 +56,8 @@ __device__ __forceinline__ uint32_t bf16_pack2(float lo, float hi) {
 }
 
 // Sum of S[ch][el*n + k], k < n, for (el, ch) items handled by groups of 8 lanes; writes the
-// 11 link observations (f, tau, count, agg_bool, agg_force) of one step to `out`.
+// 11 link observations (f, tau, count, agg_bool, agg_force) of one step to `out`, laid out
+// [11][L][E]: items run env-fastest, so neighbouring groups store neighbouring floats.
 template <class KP, class LI>
 __device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* S, int nthr, int e0, int l,
                                             float* out) {
@@ -68,7 +69,7 @@ __device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* S, int n
   for (int it0 = 0; it0 < items; it0 += groups) {
     const int it = it0 + (threadIdx.x >> 3);
     const bool ok = it < items;
-    const int ch = ok ? it % 10 : 0, el = ok ? it / 10 : 0;
+    const int ch = ok ? it / envs : 0, el = ok ? it - ch * envs : 0;
     const int e = e0 + el;
     const bool valid = ok && e < p.E;
     const float* v = S + ch * nthr + el * n;
@@ -79,7 +80,7 @@ __device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* S, int n
     acc += __shfl_xor(acc, 2, 8);
     acc += __shfl_xor(acc, 1, 8);
     if (valid && sub == 0) {
-      const int64_t col = (int64_t)e * p.L + l;
+      const int64_t col = (int64_t)l * p.E + e;
       if (ch < 6) {
         out[ch * EL + col] = acc;
       } else if (ch == 6) {
@@ -92,7 +93,9 @@ __device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* S, int n
   }
 }
 
-// Merge the LDS bit windows of this block's envs into the global [E][W] words of one step.
+// Merge the LDS bit windows of this block's envs into the global [E][W] words of one step.  The
+// words start at zero (cleared before the launch): a word inside this link is stored when it has
+// a bit set; a word shared with a neighbouring link receives this link's nonzero bits by atomic or.
 template <class KP, class LI>
 __device__ __forceinline__ void store_bits(KP& p, LI& li, const unsigned* win, int e0,
                                            unsigned long long* out_step) {
@@ -109,12 +112,12 @@ __device__ __forceinline__ void store_bits(KP& p, LI& li, const unsigned* win, i
     const int a = max(lo, gw * 64), b = min(hi, gw * 64 + 64);
     unsigned long long* dst = out_step + (int64_t)e * p.W + gw;
     if (a == gw * 64 && b == gw * 64 + 64) {
-      *dst = bits;
+      if (bits) *dst = bits;
     } else {
       const int sh = a - gw * 64, len = b - a;
       const unsigned long long cov = (len >= 64 ? ~0ull : ((1ull << len) - 1ull)) << sh;
-      atomicAnd(dst, ~cov);
-      atomicOr(dst, bits & cov);
+      const unsigned long long mine = bits & cov;
+      if (mine) atomicOr(dst, mine);
     }
   }
 }

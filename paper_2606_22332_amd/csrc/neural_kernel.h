@@ -44,7 +44,7 @@ struct NLaunch {
   float* surfdist;
   float* ft;                     // [6][E][T]
   float* normal;                 // [3][E][T]
-  float* link_sums;              // [11][E][L]
+  float* link_sums;              // [11][L][E]
 };
 
 // Counting sort of the envs by object id (ids outside [0, n_obj) form the last bin); one
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
       for (int i = tid; i < 10 * L; i += NEU_THREADS) {
         const int c = i / L, l = i - c * L;
         const float a = sums[i];
-        const int64_t col = (int64_t)e * L + l;
+        const int64_t col = (int64_t)l * E + e;
         if (c < 6) {
           q.link_sums[c * EL + col] = a;
         } else if (c == 6) {

@@ -88,7 +88,7 @@ struct KLaunch {
   float* ft;                     // [S][6][E][T]
   float* ft_noisy;
   float* normal;                 // [S][3][E][T]
-  float* link_sums;              // [S][11][E][L]
+  float* link_sums;              // [S][11][L][E]
   float* link_sums_noisy;
 };
 

@@ -51,6 +51,17 @@ __global__ void tg_reset_kernel(KParams p, const uint8_t* mask, int64_t step, fl
   p.gain[k] = fmaf(u01(x2), gain_span, gain_lo);
 }
 
+// Clear the contact-bit words of a rollout (one or two planes of n words) before the readout
+// kernel ors its bits into them.  A kernel rather than a memset, so that a captured rollout
+// holds no memset node.
+__global__ void tg_clear_words_kernel(unsigned long long* a, unsigned long long* b, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (a) a[i] = 0ull;
+    if (b) b[i] = 0ull;
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // handle
 // ------------------------------------------------------------------------------------------------
@@ -736,6 +747,12 @@ static tg_status launch_rollout(tg_readout* h, const tg_step_inputs* in, const t
   k.depth = out->depth; k.prox = out->prox; k.surfdist = out->surfdist; k.ft = out->ft; k.ft_noisy = out->ft_noisy;
   k.normal = out->normal; k.link_sums = out->link_sums; k.link_sums_noisy = out->link_sums_noisy;
   KernelFn kf = select_kernel(h->noise, h->xt, h->hy, in->obj_state ? 1 : 0, h->full);
+  if (k.bits || k.bits_noisy) {
+    const int64_t nw = (int64_t)n_steps * h->E * h->W;
+    const int64_t blocks = std::min<int64_t>((nw + 255) / 256, 16384);
+    hipLaunchKernelGGL(tg_clear_words_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, k.bits,
+                       k.bits_noisy, nw);
+  }
   hipLaunchKernelGGL(kf, dim3(h->kp.n_items_pad), dim3(h->threads), h->lds, (hipStream_t)hip_stream, k);
   if (h->thermal) {
     ThermalLaunch t{};
@@ -762,6 +779,42 @@ tg_status tg_readout_set_graph(tg_readout* h, int32_t enable) {
   if (!h) return TG_ERR_INVALID_ARGUMENT;
   h->graph_on = enable != 0;
   return TG_OK;
+}
+
+// Make `target` the handle's plan: link table, parameter block on the device, LDS attribute of
+// both kernel variants; the captured rollout graph is dropped (its launch shape changed).
+static tg_status apply_plan(tg_readout* h, int target) {
+  tg_status ps = plan_links(h, target);
+  if (ps == TG_OK && hipMemcpy(h->d_kp, &h->kp, sizeof(KParams), hipMemcpyHostToDevice) != hipSuccess) ps = TG_ERR_HIP;
+  if (ps == TG_OK) {
+    KernelFn kf = select_kernel(h->noise, h->xt, h->hy, 0, h->full);
+    KernelFn kf1 = select_kernel(h->noise, h->xt, h->hy, 1, h->full);
+    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
+    (void)hipFuncSetAttribute((const void*)kf1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
+  }
+  if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+  return ps;
+}
+
+tg_status tg_readout_set_work_plan(tg_readout* h, int32_t readouts_per_workgroup) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  h->err.clear();
+  if (h->neural) return TG_OK;
+  if (readouts_per_workgroup < 64 || readouts_per_workgroup > 1024)
+    return fail(h, TG_ERR_INVALID_ARGUMENT, "work plan: readouts per workgroup must be 64..1024");
+  if (hipDeviceSynchronize() != hipSuccess) return fail(h, TG_ERR_HIP, "work plan: device synchronisation");
+  const int prev = h->target;
+  tg_status ps = plan_links(h, readouts_per_workgroup);
+  if (ps == TG_OK && h->lds > 160 * 1024) {
+    (void)apply_plan(h, prev);
+    return fail(h, TG_ERR_INVALID_ARGUMENT, "work plan: LDS of this plan exceeds 160 KiB");
+  }
+  if (ps != TG_OK) {
+    (void)apply_plan(h, prev);
+    return fail(h, ps, "work plan: planning failed");
+  }
+  ps = apply_plan(h, readouts_per_workgroup);
+  return ps == TG_OK ? TG_OK : fail(h, ps, "work plan: upload failed");
 }
 
 tg_status tg_readout_autotune(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, int32_t n_steps,
@@ -808,15 +861,7 @@ tg_status tg_readout_autotune(tg_readout* h, const tg_step_inputs* in, const tg_
     if (rs == TG_OK) rs = tg_readout_set_state(h, saved, h->state_bytes, hip_stream);
   }
   (void)hipStreamSynchronize(st);
-  tg_status ps = plan_links(h, best);
-  if (ps == TG_OK && hipMemcpy(h->d_kp, &h->kp, sizeof(KParams), hipMemcpyHostToDevice) != hipSuccess) ps = TG_ERR_HIP;
-  if (ps == TG_OK) {
-    KernelFn kf = select_kernel(h->noise, h->xt, h->hy, 0, h->full);
-    KernelFn kf1 = select_kernel(h->noise, h->xt, h->hy, 1, h->full);
-    (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
-    (void)hipFuncSetAttribute((const void*)kf1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
-  }
-  if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+  tg_status ps = apply_plan(h, best);
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   (void)hipFree(saved);

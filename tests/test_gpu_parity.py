@@ -235,3 +235,30 @@ def test_autotune_restores_state_and_keeps_parity(torch_cuda):
     ref = oracle_ref(sc, inp)
     parity.compare(g, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
                    link_offset=sc.layout.link_offset)
+
+
+@pytest.mark.parametrize("plan", [64, 192, 512])
+def test_fixed_work_plans_keep_parity(torch_cuda, plan):
+    """tg_readout_set_work_plan: every plan gives the oracle's results (the plan only changes how
+    (link, env) work is cut into workgroups); an unsupported plan is refused and the previous one
+    kept."""
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    sc = synth.make_scene("c3", num_envs=40, num_steps=3)
+    inp = synth.make_inputs(sc)
+    d = B.to_device(inp)
+    ro = B.Readout(sc)
+    ro.alloc_outputs(3)
+    ro.set_work_plan(plan)
+    assert ro.launch_shape()[0] == plan
+    with pytest.raises(B.TgError):
+        ro.set_work_plan(2048)
+    assert ro.launch_shape()[0] == plan
+    ro.rollout(d, 3)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in ro.out.items()}
+    ro.out = {}
+    ro.close()
+    ref = oracle_ref(sc, inp)
+    parity.compare(g, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
+                   link_offset=sc.layout.link_offset)
