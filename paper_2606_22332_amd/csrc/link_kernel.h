@@ -55,40 +55,57 @@ __device__ __forceinline__ uint32_t bf16_pack2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector((f2){lo, hi}, bf2));
 }
 
-// Sum of S[ch][el*n + k], k < n, for (el, ch) items handled by groups of 8 lanes; writes the
-// 11 link observations (f, tau, count, agg_bool, agg_force) of one step to `out`, laid out
-// [11][L][E]: items run env-fastest, so neighbouring groups store neighbouring floats.
+// Sum over each aligned group of 8 lanes (three DPP adds); the total is valid in the group's
+// first lane, added as ((a0+a1)+(a2+a3))+((a4+a5)+(a6+a7)).  Called with every lane active.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float group8_sum(float v) {
+  v = v + dpp_f<0xB1>(v);    // quad_perm [1,0,3,2]
+  v = v + dpp_f<0x4E>(v);    // quad_perm [2,3,0,1]
+  v = v + dpp_f<0x104>(v);   // row_shl:4 (lane i takes lane i + 4)
+  return v;
+}
+
+// The 10 summed channels of one step (f, tau, contact, d * n_z, d * n_y, d * n_x), reduced over
+// each 8-lane group and parked as P[ch][group] by the group's first lane.  An env's lanes are a
+// whole number of groups (n_l padded to a multiple of 8), so every group belongs to one env;
+// lanes outside a readout pass zeros.
+__device__ __forceinline__ void put_group_sums(float* P, int ngroups, const float* v) {
+  const bool lead = (threadIdx.x & 7) == 0;
+  const int g = threadIdx.x >> 3;
+#pragma unroll
+  for (int c = 0; c < 10; ++c) {
+    const float t = group8_sum(v[c]);
+    if (lead) P[c * ngroups + g] = t;
+  }
+}
+
+// Per-link observations of one step (App. B.2: summed force and torque, contact count, agg_bool,
+// agg_force) from the group partials: one lane per (channel, env) item adds the env's groups in
+// order; output [11][L][E], items env-fastest so neighbouring lanes store neighbouring floats.
 template <class KP, class LI>
-__device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* S, int nthr, int e0, int l,
+__device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* P, int ngroups, int e0, int l,
                                             float* out) {
-  const int n = li.n, envs = li.envs;
+  const int envs = li.envs, gpe = li.np >> 3;
   const int items = envs * 10;
-  const int groups = blockDim.x >> 3;
-  const int sub = threadIdx.x & 7;
   const int64_t EL = (int64_t)p.E * p.L;
-  for (int it0 = 0; it0 < items; it0 += groups) {
-    const int it = it0 + (threadIdx.x >> 3);
-    const bool ok = it < items;
-    const int ch = ok ? it / envs : 0, el = ok ? it - ch * envs : 0;
+  for (int it = threadIdx.x; it < items; it += blockDim.x) {
+    const int ch = it / envs, el = it - ch * envs;
     const int e = e0 + el;
-    const bool valid = ok && e < p.E;
-    const float* v = S + ch * nthr + el * n;
+    if (e >= p.E) continue;
+    const float* v = P + ch * ngroups + el * gpe;
     float acc = 0.f;
-    if (valid)
-      for (int k = sub; k < n; k += 8) acc += v[k];
-    acc += __shfl_xor(acc, 4, 8);
-    acc += __shfl_xor(acc, 2, 8);
-    acc += __shfl_xor(acc, 1, 8);
-    if (valid && sub == 0) {
-      const int64_t col = (int64_t)l * p.E + e;
-      if (ch < 6) {
-        out[ch * EL + col] = acc;
-      } else if (ch == 6) {
-        out[6 * EL + col] = acc;
-        out[7 * EL + col] = acc > 2.5f ? 1.f : 0.f;
-      } else {
-        out[(ch + 1) * EL + col] = 1.0e4f * acc;
-      }
+    for (int g = 0; g < gpe; ++g) acc += v[g];
+    const int64_t col = (int64_t)l * p.E + e;
+    if (ch < 6) {
+      out[ch * EL + col] = acc;
+    } else if (ch == 6) {
+      out[6 * EL + col] = acc;
+      out[7 * EL + col] = acc > 2.5f ? 1.f : 0.f;
+    } else {
+      out[(ch + 1) * EL + col] = 1.0e4f * acc;
     }
   }
 }
@@ -169,10 +186,11 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
   float* RAW = (float*)(smem + Ld.raw);      // [2][14][envs] prefetched step inputs
   const int winw = envs * li.nwin * 2;       // u32 words of one bit-window set
 
-  const int el = tid / n;
-  const int k = tid - el * n;
+  const int np = li.np;                      // lanes per env (n padded to a multiple of 8)
+  const int el = tid / np;
+  const int k = tid - el * np;
   const int e = e0 + el;
-  const bool act = tid < envs * n && e < p.E;
+  const bool act = el < envs && k < n && e < p.E;
   const int j = li.off + k;
   const int64_t ET = (int64_t)p.E * p.T;
   const int64_t EL = (int64_t)p.E * p.L;
@@ -288,13 +306,11 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
       if (bit) atomicOr(&bw[el * li.nwin * 2 + (wbit >> 5)], 1u << (wbit & 31));
     }
     const bool sums = q.link_sums != nullptr;
-    if (sums) {
-      S[0 * nthr + tid] = o.f[0]; S[1 * nthr + tid] = o.f[1]; S[2 * nthr + tid] = o.f[2];
-      S[3 * nthr + tid] = o.tau[0]; S[4 * nthr + tid] = o.tau[1]; S[5 * nthr + tid] = o.tau[2];
-      S[6 * nthr + tid] = bit ? 1.f : 0.f;
-      S[7 * nthr + tid] = o.depth * tb.z;
-      S[8 * nthr + tid] = o.depth * tb.y;
-      S[9 * nthr + tid] = o.depth * tb.x;
+    const int ngroups = nthr >> 3;
+    if (sums) {   // (o and tb are zero outside a readout)
+      const float v[10] = {o.f[0], o.f[1], o.f[2], o.tau[0], o.tau[1], o.tau[2], bit ? 1.f : 0.f,
+                           o.depth * tb.z, o.depth * tb.y, o.depth * tb.x};
+      put_group_sums(S, ngroups, v);
     }
     float z[6] = {gain * o.f[0], gain * o.f[1], gain * o.f[2], gain * o.tau[0], gain * o.tau[1], gain * o.tau[2]};
     if (NOISE && XT == 1) {
@@ -314,7 +330,7 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
     __syncthreads();   // B2: clean bits, sums, crosstalk operands
     TG_REFRESH_PHASE();
     if (q.bits) store_bits(p, li, bw, e0, q.bits + (int64_t)s * p.E * p.W);
-    if (sums) link_reduce(p, li, S, nthr, e0, l, q.link_sums + (int64_t)s * 11 * EL);
+    if (sums) link_reduce(p, li, S, ngroups, e0, l, q.link_sums + (int64_t)s * 11 * EL);
 
     if (NOISE) {
       if (XT == 2) {
@@ -457,18 +473,16 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
       const bool sums_n = q.link_sums_noisy != nullptr;
       if (sums_n) {
         const float4 tn = act ? TX[2 * k + 1] : make_float4(0.f, 0.f, 0.f, 0.f);
-        S[0 * nthr + tid] = fo[0]; S[1 * nthr + tid] = fo[1]; S[2 * nthr + tid] = fo[2];
-        S[3 * nthr + tid] = fo[3]; S[4 * nthr + tid] = fo[4]; S[5 * nthr + tid] = fo[5];
-        S[6 * nthr + tid] = nb ? 1.f : 0.f;
-        S[7 * nthr + tid] = dd * tn.z;
-        S[8 * nthr + tid] = dd * tn.y;
-        S[9 * nthr + tid] = dd * tn.x;
+        const float v[10] = {act ? fo[0] : 0.f, act ? fo[1] : 0.f, act ? fo[2] : 0.f,
+                             act ? fo[3] : 0.f, act ? fo[4] : 0.f, act ? fo[5] : 0.f,
+                             act && nb ? 1.f : 0.f, dd * tn.z, dd * tn.y, dd * tn.x};
+        put_group_sums(S, ngroups, v);
       }
       if (pre && pf_off != -1) RAW[(par ^ 1) * nraw + tid] = rv;   // park the next step's inputs
       __syncthreads();   // B4: noisy bits and sums
       TG_REFRESH_PHASE();
       if (q.bits_noisy) store_bits(p, li, bwn, e0, q.bits_noisy + (int64_t)s * p.E * p.W);
-      if (sums_n) link_reduce(p, li, S, nthr, e0, l, q.link_sums_noisy + (int64_t)s * 11 * EL);
+      if (sums_n) link_reduce(p, li, S, ngroups, e0, l, q.link_sums_noisy + (int64_t)s * 11 * EL);
     }
   }
   TG_REFRESH();

@@ -26,6 +26,7 @@ struct LinkInfo {
   int32_t mt, kt, nt;    // dense crosstalk: M tiles, K tiles (16 rows each), N tiles of 16 columns
   int32_t kp, kpd;       // padded K stride (bf16 elements) of the B staging, of the result staging
   int32_t afrag_off;     // first A tile of this link in the fragment buffer
+  int32_t np;            // lanes per env: n rounded up to a multiple of 8 (aligned 8-lane groups)
 };
 
 // LDS carve-up (byte offsets), identical for every block of a launch.

@@ -150,13 +150,14 @@ tg_status plan_links(tg_readout* h, int target) {
     if (li.n > 512) return TG_ERR_UNSUPPORTED;
     // envs per block: ~target readouts, at most 36 envs so that the 14 prefetched scalars per env
     // fit one per lane
-    li.envs = li.n > 0 ? std::max(1, std::min(std::min(E, 36), target / li.n)) : 1;
+    li.np = li.n > 0 ? (li.n + 7) & ~7 : 8;   // lanes per env: whole 8-lane groups
+    li.envs = std::max(1, std::min(std::min(E, 36), target / li.np));
     li.nwin = li.n > 0 ? ((li.off + li.n - 1) >> 6) - (li.off >> 6) + 1 : 1;
     li.nt = (6 * li.envs + 15) / 16;
     const int n16 = ((li.n + 15) / 16) * 16;
     li.kp = n16 + 8;
     li.kpd = n16 + 4;
-    nthr = std::max(nthr, ((li.envs * li.n + 63) / 64) * 64);
+    nthr = std::max(nthr, ((li.envs * li.np + 63) / 64) * 64);
   }
   {  // the per-step input prefetch parks 14 scalars per env, one per lane
     int max_envs = 1;
@@ -183,7 +184,7 @@ tg_status plan_links(tg_readout* h, int target) {
   d.opose = (int32_t)o; o = align16i(o + 2 * pose * (int64_t)sizeof(Pose));
   d.oid = (int32_t)o; o = align16i(o + 2 * pose * 4);
   d.bits = (int32_t)o; o = align16i(o + 2 * 2 * bits * 4);
-  d.sums = (int32_t)o; o = align16i(o + 10 * (int64_t)nthr * 4);
+  d.sums = (int32_t)o; o = align16i(o + 10 * (int64_t)(nthr / 8) * 4);
   d.xz = (int32_t)o; o = align16i(o + (h->xt == 1 ? 6 * (int64_t)nthr * 4 : 0));
   d.tax = (int32_t)o; o = align16i(o + tax);
   h->kp.gtab_lds = h->n_obj <= 256;
