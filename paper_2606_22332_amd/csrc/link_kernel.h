@@ -45,8 +45,11 @@ __device__ __forceinline__ Pose pose_from13(const float* v) {
   return P;
 }
 
-// Store through a uniform base and a per-lane 32-bit byte offset (scalar-base addressing).
-__device__ __forceinline__ void store_at(float* base, uint32_t off4, float v) { *(float*)((char*)base + off4) = v; }
+// Outputs are written once and never read back by the kernel: non-temporal stores, so that the
+// output stream does not evict the grid bricks the gathers reuse from L2.
+__device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+// Store through a uniform base and a per-lane 32-bit byte offset.
+__device__ __forceinline__ void store_at(float* base, uint32_t off4, float v) { store_nt((float*)((char*)base + off4), v); }
 
 // Two FP32 values rounded to BF16 (nearest even), packed low, high (one v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint32_t bf16_pack2(float lo, float hi) {
@@ -82,30 +85,41 @@ __device__ __forceinline__ void put_group_sums(float* P, int ngroups, const floa
   }
 }
 
+// A lane's roles in the per-step epilogues, fixed for the launch and packed in one register (byte
+// fields): link sums (channel, env) for lane = channel * envs + env, bit words (env, word) for
+// lane = env * nwin + word.  The plan gives every workgroup at least 14 lanes per env, so each
+// epilogue takes a single pass and the integer divisions happen once, before the step loop.
+__device__ __forceinline__ uint32_t lane_roles(int tid, int envs, int nwin) {
+  const int rch = tid / envs, rel = tid - rch * envs;
+  const int bel = tid / nwin, bw = tid - bel * nwin;
+  const bool rok = rch < 10, bok = bel < envs;
+  return (rok ? (uint32_t)rch | ((uint32_t)rel << 8) : 0xffffu) | (bok ? ((uint32_t)bel << 16) | ((uint32_t)bw << 24) : 0xffff0000u);
+}
+
 // Per-link observations of one step (App. B.2: summed force and torque, contact count, agg_bool,
 // agg_force) from the group partials: one lane per (channel, env) item adds the env's groups in
 // order; output [11][L][E], items env-fastest so neighbouring lanes store neighbouring floats.
 template <class KP, class LI>
 __device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* P, int ngroups, int e0, int l,
-                                            float* out) {
-  const int envs = li.envs, gpe = li.np >> 3;
-  const int items = envs * 10;
+                                            float* out, uint32_t roles) {
+  const int gpe = li.np >> 3;
   const int64_t EL = (int64_t)p.E * p.L;
-  for (int it = threadIdx.x; it < items; it += blockDim.x) {
-    const int ch = it / envs, el = it - ch * envs;
+  {
+    const int ch = roles & 0xffu, el = (roles >> 8) & 0xffu;
+    if (ch >= 10) return;
     const int e = e0 + el;
-    if (e >= p.E) continue;
+    if (e >= p.E) return;
     const float* v = P + ch * ngroups + el * gpe;
     float acc = 0.f;
     for (int g = 0; g < gpe; ++g) acc += v[g];
     const int64_t col = (int64_t)l * p.E + e;
     if (ch < 6) {
-      out[ch * EL + col] = acc;
+      store_nt(out + ch * EL + col, acc);
     } else if (ch == 6) {
-      out[6 * EL + col] = acc;
-      out[7 * EL + col] = acc > 2.5f ? 1.f : 0.f;
+      store_nt(out + 6 * EL + col, acc);
+      store_nt(out + 7 * EL + col, acc > 2.5f ? 1.f : 0.f);
     } else {
-      out[(ch + 1) * EL + col] = 1.0e4f * acc;
+      store_nt(out + (ch + 1) * EL + col, 1.0e4f * acc);
     }
   }
 }
@@ -115,21 +129,22 @@ __device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* P, int n
 // a bit set; a word shared with a neighbouring link receives this link's nonzero bits by atomic or.
 template <class KP, class LI>
 __device__ __forceinline__ void store_bits(KP& p, LI& li, const unsigned* win, int e0,
-                                           unsigned long long* out_step) {
+                                           unsigned long long* out_step, uint32_t roles) {
   const int nw = li.nwin;
   const int wstart = li.off >> 6;
   const int lo = li.off, hi = li.off + li.n;
-  for (int idx = threadIdx.x; idx < li.envs * nw; idx += blockDim.x) {
-    const int el = idx / nw, w = idx - el * nw;
+  {
+    const int el = (roles >> 16) & 0xffu, w = roles >> 24;
+    if (el >= li.envs) return;
     const int e = e0 + el;
-    if (e >= p.E) continue;
+    if (e >= p.E) return;
     const unsigned long long bits =
         (unsigned long long)win[(el * nw + w) * 2] | ((unsigned long long)win[(el * nw + w) * 2 + 1] << 32);
     const int gw = wstart + w;
     const int a = max(lo, gw * 64), b = min(hi, gw * 64 + 64);
     unsigned long long* dst = out_step + (int64_t)e * p.W + gw;
     if (a == gw * 64 && b == gw * 64 + 64) {
-      if (bits) *dst = bits;
+      if (bits) __builtin_nontemporal_store(bits, dst);
     } else {
       const int sh = a - gw * 64, len = b - a;
       const unsigned long long cov = (len >= 64 ? ~0ull : ((1ull << len) - 1ull)) << sh;
@@ -198,6 +213,7 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
   // byte offset of (e, j) in an [E][T] plane: fits 32 bits (checked at create), so every output
   // store is a uniform per-step base plus this fixed lane offset
   const uint32_t off4 = (uint32_t)kk * 4u;
+  const uint32_t roles = lane_roles(tid, envs, li.nwin);
 
   for (int i = tid; i < n; i += nthr) {
     TX[2 * i] = p.taxA[li.off + i];
@@ -329,8 +345,8 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
     if (!NOISE && pre && pf_off != -1) RAW[(par ^ 1) * nraw + tid] = rv;   // the other parity is free
     __syncthreads();   // B2: clean bits, sums, crosstalk operands
     TG_REFRESH_PHASE();
-    if (q.bits) store_bits(p, li, bw, e0, q.bits + (int64_t)s * p.E * p.W);
-    if (sums) link_reduce(p, li, S, ngroups, e0, l, q.link_sums + (int64_t)s * 11 * EL);
+    if (q.bits) store_bits(p, li, bw, e0, q.bits + (int64_t)s * p.E * p.W, roles);
+    if (sums) link_reduce(p, li, S, ngroups, e0, l, q.link_sums + (int64_t)s * 11 * EL, roles);
 
     if (NOISE) {
       if (XT == 2) {
@@ -481,8 +497,8 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
       if (pre && pf_off != -1) RAW[(par ^ 1) * nraw + tid] = rv;   // park the next step's inputs
       __syncthreads();   // B4: noisy bits and sums
       TG_REFRESH_PHASE();
-      if (q.bits_noisy) store_bits(p, li, bwn, e0, q.bits_noisy + (int64_t)s * p.E * p.W);
-      if (sums_n) link_reduce(p, li, S, ngroups, e0, l, q.link_sums_noisy + (int64_t)s * 11 * EL);
+      if (q.bits_noisy) store_bits(p, li, bwn, e0, q.bits_noisy + (int64_t)s * p.E * p.W, roles);
+      if (sums_n) link_reduce(p, li, S, ngroups, e0, l, q.link_sums_noisy + (int64_t)s * 11 * EL, roles);
     }
   }
   TG_REFRESH();

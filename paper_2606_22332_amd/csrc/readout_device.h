@@ -11,14 +11,18 @@
 
 namespace tg {
 
+// A cubic SDF grid of n^3 samples.  The readout stores it in bricks of 4 x 4 x 4 values (256 B):
+// sample (x, y, z) lives at offset + ((z/4 * nb + y/4) * nb + x/4) * 64 + (z%4 * 4 + y%4) * 4 + x%4,
+// nb = ceil(n/4), so the 8 corners of a cell fall in one or two 128-byte lines and neighbouring
+// probes of a patch share bricks.  (The training-target kernels keep plain x-fastest order, nb = 0.)
 struct GridDesc {
   float origin[3];
   float spacing;
   float hinv;      // RN(1 / spacing), computed once on the host in FP32
   float nm1;       // (float)(n - 1)
   int32_t n;
-  int32_t pad;
-  int64_t offset;  // first value in the concatenated grid buffer
+  int32_t nb;      // bricks per axis
+  int64_t offset;  // first value (a brick boundary) in the concatenated grid buffer
 };
 
 struct Pose {     // rotation, position, velocity, angular velocity

@@ -138,17 +138,26 @@ __device__ __forceinline__ void grid_lookup(const GridDesc& g, const float* grid
     ii[i] = k;
     h.t[i] = uc[i] - (float)k;
   }
-  // 32-bit byte offsets from the (uniform) base of all grids: the loads use a scalar base
-  const int N = g.n;
-  const uint32_t base = (uint32_t)g.offset + ((uint32_t)ii[2] * (uint32_t)N + (uint32_t)ii[1]) * (uint32_t)N +
-                        (uint32_t)ii[0];
-  const uint32_t sy = (uint32_t)N, sz = (uint32_t)N * (uint32_t)N;
+  // Brick addressing, separable per axis (element units): x -> (x/4)*64 + x%4,
+  // y -> (y/4)*64nb + (y%4)*4, z -> (z/4)*64nb^2 + (z%4)*16; the +1 corner steps into the next
+  // brick when the cell sits on a brick's last row.  32-bit byte offsets from the uniform base of
+  // all grids, so the loads use a scalar base.
+  const uint32_t nb = (uint32_t)g.nb;
+  const uint32_t x0 = (uint32_t)ii[0], y0 = (uint32_t)ii[1], z0 = (uint32_t)ii[2];
+  const uint32_t sy = nb << 6, sz = sy * nb;
+  const uint32_t ax0 = ((x0 >> 2) << 6) + (x0 & 3u);
+  const uint32_t ax1 = ax0 + ((x0 & 3u) == 3u ? 61u : 1u);
+  const uint32_t ay0 = (y0 >> 2) * sy + ((y0 & 3u) << 2);
+  const uint32_t ay1 = ay0 + ((y0 & 3u) == 3u ? sy - 12u : 4u);
+  const uint32_t az0 = (z0 >> 2) * sz + ((z0 & 3u) << 4);
+  const uint32_t az1 = az0 + ((z0 & 3u) == 3u ? sz - 48u : 16u);
+  const uint32_t base = (uint32_t)g.offset;
+  const uint32_t r00 = base + ay0 + az0, r10 = base + ay1 + az0, r01 = base + ay0 + az1, r11 = base + ay1 + az1;
   const char* Gb = (const char*)grid_vals;
-  const uint32_t o0 = base * 4u, oy = (base + sy) * 4u, oz = (base + sz) * 4u, oyz = (base + sz + sy) * 4u;
-  h.c000 = *(const float*)(Gb + o0); h.c100 = *(const float*)(Gb + o0 + 4u);
-  h.c010 = *(const float*)(Gb + oy); h.c110 = *(const float*)(Gb + oy + 4u);
-  h.c001 = *(const float*)(Gb + oz); h.c101 = *(const float*)(Gb + oz + 4u);
-  h.c011 = *(const float*)(Gb + oyz); h.c111 = *(const float*)(Gb + oyz + 4u);
+  h.c000 = *(const float*)(Gb + (r00 + ax0) * 4u); h.c100 = *(const float*)(Gb + (r00 + ax1) * 4u);
+  h.c010 = *(const float*)(Gb + (r10 + ax0) * 4u); h.c110 = *(const float*)(Gb + (r10 + ax1) * 4u);
+  h.c001 = *(const float*)(Gb + (r01 + ax0) * 4u); h.c101 = *(const float*)(Gb + (r01 + ax1) * 4u);
+  h.c011 = *(const float*)(Gb + (r11 + ax0) * 4u); h.c111 = *(const float*)(Gb + (r11 + ax1) * 4u);
   const float* t = h.t;
   const float l00 = lerpf(t[0], h.c000, h.c100), l10 = lerpf(t[0], h.c010, h.c110);
   const float l01 = lerpf(t[0], h.c001, h.c101), l11 = lerpf(t[0], h.c011, h.c111);

@@ -475,7 +475,7 @@ tg_status tg_nsdf_create(const tg_nsdf_config* cfg, tg_nsdf** out) {
     b.grid.hinv = 1.0f / g.spacing;
     b.grid.nm1 = (float)(g.n - 1);
     b.grid.n = g.n;
-    b.grid.pad = 0;
+    b.grid.nb = 0;        // plain x-fastest order here (grid_value), not bricks
     b.grid.offset = total;
     const float ext = (float)(g.n - 1) * g.spacing;
     b.half = 0.5f * ext;

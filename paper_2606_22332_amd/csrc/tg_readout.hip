@@ -26,6 +26,21 @@ thread_local std::string g_create_error;
 
 inline int32_t align16i(int64_t x) { return (int32_t)((x + 15) & ~int64_t(15)); }
 
+// Values of an n^3 grid in 4 x 4 x 4 bricks (the layout GridDesc describes), zero padded.
+inline int64_t brick_values(int n) {
+  const int64_t nb = (n + 3) / 4;
+  return nb * nb * nb * 64;
+}
+void to_bricks(const float* v, int n, float* out) {
+  const int nb = (n + 3) / 4;
+  for (int z = 0; z < n; ++z)
+    for (int y = 0; y < n; ++y)
+      for (int x = 0; x < n; ++x) {
+        const int64_t b = ((int64_t)(z >> 2) * nb + (y >> 2)) * nb + (x >> 2);
+        out[b * 64 + ((z & 3) * 4 + (y & 3)) * 4 + (x & 3)] = v[((int64_t)z * n + y) * n + x];
+      }
+}
+
 }  // namespace
 
 // Episode reset: zero the dynamic state and draw dead flag, stuck value and gain with
@@ -165,6 +180,8 @@ tg_status plan_links(tg_readout* h, int target) {
     nthr = std::max(nthr, ((14 * max_envs + 63) / 64) * 64);
   }
   if (nthr > 512) return TG_ERR_UNSUPPORTED;
+  for (int l = 0; l < L; ++l)   // the per-step epilogues take one pass: one lane per item
+    if (10 * h->links[l].envs > nthr || h->links[l].envs * h->links[l].nwin > nthr) return TG_ERR_UNSUPPORTED;
   h->threads = nthr;
   // LDS layout: max over links of each region
   int64_t pose = 0, bits = 0, bt = 0, dt = 0, tax = 0;
@@ -362,8 +379,8 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
   h->noise = noise;
   h->xt = noise ? nz.xtalk_kind : 0;
   h->hy = noise ? nz.hyst_mode : 0;
-  int64_t total_vals = 0;
-  for (int g = 0; g < NO; ++g) total_vals += (int64_t)cfg->grids[g].n * cfg->grids[g].n * cfg->grids[g].n;
+  int64_t total_vals = 0;   // bricked: ceil(n/4)^3 bricks of 64 values per grid
+  for (int g = 0; g < NO; ++g) total_vals += brick_values(cfg->grids[g].n);
   if (total_vals * 4 > (int64_t)0xffffffffLL) {   // grid corners are addressed with 32-bit byte offsets
     delete h;
     return fail(nullptr, TG_ERR_UNSUPPORTED, "grid values exceed 4 GiB");
@@ -391,9 +408,9 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     gd[g].hinv = one / G.spacing;
     gd[g].nm1 = (float)(G.n - 1);
     gd[g].n = G.n;
-    gd[g].pad = 0;
+    gd[g].nb = (G.n + 3) / 4;
     gd[g].offset = goff;
-    goff += (int64_t)G.n * G.n * G.n;
+    goff += brick_values(G.n);
   }
 
   KParams& k = h->kp;
@@ -425,7 +442,9 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
   if (e == hipSuccess) e = hipMemcpy(dG, gd.data(), NO * sizeof(GridDesc), hipMemcpyHostToDevice);
   for (int g = 0; g < NO && e == hipSuccess; ++g) {
     const tg_sdf_grid& G = cfg->grids[g];
-    e = hipMemcpy(dV + gd[g].offset, G.values, (size_t)G.n * G.n * G.n * sizeof(float), hipMemcpyHostToDevice);
+    std::vector<float> bricks((size_t)brick_values(G.n), 0.f);
+    to_bricks(G.values, G.n, bricks.data());
+    e = hipMemcpy(dV + gd[g].offset, bricks.data(), bricks.size() * sizeof(float), hipMemcpyHostToDevice);
   }
   if (e != hipSuccess) {
     tg_readout_destroy(h);
