@@ -154,6 +154,8 @@ __device__ __forceinline__ void store_bits(KP& p, LI& li, const unsigned* win, i
   }
 }
 
+// XT: crosstalk 0 none, 1 banded, 2 dense with the link's A fragments staged in LDS for the
+// launch, 3 dense with them read from L2 each step (plans where they do not fit beside the rest).
 // FULL = 0 compiles out the knobs none of the shipped workloads use (white noise, bias,
 // quantisation, per-probe gain, probe-radius noise, normal / surface-distance outputs) so that
 // the common path fits in 128 VGPRs (4 waves per SIMD) without spilling.
@@ -189,7 +191,7 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
   LinkLds Ld;   // field by field: the source lives in the constant address space
   Ld.pose = p.lds.pose; Ld.opose = p.lds.opose; Ld.oid = p.lds.oid; Ld.bits = p.lds.bits; Ld.sums = p.lds.sums;
   Ld.xz = p.lds.xz; Ld.tax = p.lds.tax; Ld.gtab = p.lds.gtab; Ld.raw = p.lds.raw; Ld.bt = p.lds.bt; Ld.dt = p.lds.dt;
-  Ld.total = p.lds.total;
+  Ld.afr = p.lds.afr; Ld.total = p.lds.total;
   Pose* lpose = (Pose*)(smem + Ld.pose);
   Pose* opose = (Pose*)(smem + Ld.opose);
   int* oids = (int*)(smem + Ld.oid);
@@ -253,9 +255,14 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
     if (p.has_stuck) stuck = p.stuck[kk];
     if (FULL && p.has_gain) gain = p.gain[kk];
   }
-  if (XT == 2) {   // zero the B staging once: padding rows and columns stay zero
+  if (XT >= 2) {   // zero the B staging once: padding rows and columns stay zero
     uint32_t* bt = (uint32_t*)(smem + Ld.bt);
     for (int i = tid; i < (li.nt * 16 * li.kp) / 2; i += nthr) bt[i] = 0u;
+    if (XT == 2) {   // the link's A fragments, read from LDS at every step
+      uint2* af = (uint2*)(smem + Ld.afr);
+      const uint2* src = p.xt_afrag + (int64_t)li.afrag_off * 64;
+      for (int i = tid; i < li.mt * li.kt * 64; i += nthr) af[i] = src[i];
+    }
   }
   const bool loader = tid < envs && e0 + tid < p.E;
   __syncthreads();   // LDS constants and the first step's inputs
@@ -333,7 +340,7 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
 #pragma unroll
       for (int c = 0; c < 6; ++c) XZ[c * nthr + tid] = z[c];
     }
-    if (NOISE && XT == 2 && act) {
+    if (NOISE && XT >= 2 && act) {
       uint16_t* bt = (uint16_t*)(smem + Ld.bt);
 #pragma unroll
       for (int c = 0; c < 6; c += 2) {
@@ -349,9 +356,10 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
     if (sums) link_reduce(p, li, S, ngroups, e0, l, q.link_sums + (int64_t)s * 11 * EL, roles);
 
     if (NOISE) {
-      if (XT == 2) {
+      if (XT >= 2) {
         // C_l Z on MFMA.  Wave w takes M tile w % MT and every G-th N tile (G = waves per M tile),
-        // so it fetches its A fragments (one per K tile, L2-resident) once per step.
+        // so it reads its A fragments (one per K tile; from LDS when the plan stages them, else
+        // from L2) once per step.
         const uint16_t* bt = (const uint16_t*)(smem + Ld.bt);
         float* dt = (float*)(smem + Ld.dt);
         const int lane = tid & 63, wave = tid >> 6, nwaves = nthr >> 6;
@@ -359,9 +367,11 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
         const int G = nwaves >= li.mt ? nwaves / li.mt : 1;
         for (int mt = wave % li.mt; mt < li.mt && wave < G * li.mt; mt += nwaves) {
           const uint2* arow = p.xt_afrag + ((int64_t)li.afrag_off + (int64_t)mt * li.kt) * 64 + lane;
+          const uint2* lrow = (const uint2*)(smem + Ld.afr) + mt * li.kt * 64 + lane;
+          const uint2* asrc = XT == 2 ? lrow : arow;
           uint2 afr[8];
 #pragma unroll
-          for (int kt = 0; kt < 8; ++kt) afr[kt] = kt < li.kt ? arow[kt * 64] : make_uint2(0u, 0u);
+          for (int kt = 0; kt < 8; ++kt) afr[kt] = kt < li.kt ? asrc[kt * 64] : make_uint2(0u, 0u);
           for (int nt = (nwaves >= li.mt ? wave / li.mt : 0); nt < li.nt; nt += G) {
             const int col = nt * 16 + (lane & 15);
             const uint16_t* bcol = bt + col * li.kp + 4 * (lane >> 4);
@@ -377,7 +387,7 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
               }
             }
             for (int kt = 8; kt < li.kt; ++kt) {   // links of more than 128 taxels
-              const uint2 a = arow[kt * 64];
+              const uint2 a = asrc[kt * 64];
               const uint2 b = *(const uint2*)(bcol + 16 * kt);
               bf16x4 av, bv;
               __builtin_memcpy(&av, &a, 8);
@@ -406,7 +416,7 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
           if (act && hasr) acc = fmaf(chi, XZ[c * nthr + tid + 1], acc);
           zt[c] = acc;
         }
-      } else if (XT == 2) {
+      } else if (XT >= 2) {
         const float* dt = (const float*)(smem + Ld.dt);
 #pragma unroll
         for (int c = 0; c < 6; ++c) zt[c] = act ? dt[(6 * el + c) * li.kpd + k] : 0.f;

@@ -31,7 +31,7 @@ struct LinkInfo {
 
 // LDS carve-up (byte offsets), identical for every block of a launch.
 struct LinkLds {
-  int32_t pose, opose, oid, bits, sums, xz, tax, gtab, raw, bt, dt, total;
+  int32_t pose, opose, oid, bits, sums, xz, tax, gtab, raw, bt, dt, afr, total;
 };
 
 struct KParams {
@@ -65,6 +65,7 @@ struct KParams {
   const LinkInfo* links;         // [L]
   int32_t n_items, n_items_pad;  // pad = multiple of 8 (XCD-aware remapping)
   int32_t gtab_lds;              // 1: grid descriptors staged in LDS
+  int32_t afr_lds;               // 1: the link's dense crosstalk A fragments staged in LDS
   LinkLds lds;
   // dense crosstalk (kind 2)
   const uint2* xt_afrag;         // A fragments, 4 bf16 per lane, 64 lanes per 16x16 tile

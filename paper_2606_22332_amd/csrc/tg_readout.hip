@@ -144,9 +144,14 @@ KernelFn select_kernel_f(int noise, int xt, int hy, int obj) {
   TG_PICK(0, 0) TG_PICK(0, 1) TG_PICK(0, 2)
   TG_PICK(1, 0) TG_PICK(1, 1) TG_PICK(1, 2)
   TG_PICK(2, 0) TG_PICK(2, 1) TG_PICK(2, 2)
+  TG_PICK(3, 0) TG_PICK(3, 1) TG_PICK(3, 2)
 #undef TG_PICK
   return nullptr;
 }
+
+// Crosstalk variant of the readout kernel: the dense kind reads its A fragments from LDS when
+// the plan staged them, else from L2.
+int kernel_xt(const tg_readout* h) { return h->xt == 2 && !h->kp.afr_lds ? 3 : h->xt; }
 
 KernelFn select_kernel(int noise, int xt, int hy, int obj, int full) {
   return full ? select_kernel_f<1>(noise, xt, hy, obj) : select_kernel_f<0>(noise, xt, hy, obj);
@@ -209,6 +214,12 @@ tg_status plan_links(tg_readout* h, int target) {
   d.raw = (int32_t)o; o = align16i(o + 2 * 14 * pose * 4);
   d.bt = (int32_t)o; o = align16i(o + bt);
   d.dt = (int32_t)o; o = align16i(o + dt);
+  // the dense crosstalk A fragments of the largest link, resident in LDS when they fit
+  int64_t afr = 0;
+  if (h->xt == 2)
+    for (int l = 0; l < L; ++l) afr = std::max<int64_t>(afr, (int64_t)h->links[l].mt * h->links[l].kt * 64 * 8);
+  h->kp.afr_lds = (h->xt == 2 && afr > 0 && align16i(o + afr) <= 160 * 1024) ? 1 : 0;
+  d.afr = (int32_t)o; o = align16i(o + (h->kp.afr_lds ? afr : 0));
   d.total = (int32_t)o;
   h->lds = (size_t)o;
   // items, env-major so that neighbouring blocks share envs (and objects)
@@ -526,8 +537,8 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
   h->full = (noise && (nz.white_sigma != 0.f || nz.bias != 0.f || nz.quant_step > 0.f || nz.radius_rho > 0.f ||
                         !(nz.gain_lo == 1.0f && nz.gain_hi == 1.0f))) ||
             (om & (TG_OUT_NORMAL | TG_OUT_SURFDIST)) != 0;
-  KernelFn kf = select_kernel(noise, h->xt, h->hy, 0, h->full);
-  KernelFn kf1 = select_kernel(noise, h->xt, h->hy, 1, h->full);
+  KernelFn kf = select_kernel(noise, kernel_xt(h), h->hy, 0, h->full);
+  KernelFn kf1 = select_kernel(noise, kernel_xt(h), h->hy, 1, h->full);
   if (!kf || !kf1) {
     tg_readout_destroy(h);
     return fail(nullptr, TG_ERR_UNSUPPORTED, "no kernel for this noise configuration");
@@ -766,7 +777,7 @@ static tg_status launch_rollout(tg_readout* h, const tg_step_inputs* in, const t
   k.bits_noisy = (unsigned long long*)out->contact_bits_noisy;
   k.depth = out->depth; k.prox = out->prox; k.surfdist = out->surfdist; k.ft = out->ft; k.ft_noisy = out->ft_noisy;
   k.normal = out->normal; k.link_sums = out->link_sums; k.link_sums_noisy = out->link_sums_noisy;
-  KernelFn kf = select_kernel(h->noise, h->xt, h->hy, in->obj_state ? 1 : 0, h->full);
+  KernelFn kf = select_kernel(h->noise, kernel_xt(h), h->hy, in->obj_state ? 1 : 0, h->full);
   if (k.bits || k.bits_noisy) {
     const int64_t nw = (int64_t)n_steps * h->E * h->W;
     const int64_t blocks = std::min<int64_t>((nw + 255) / 256, 16384);
@@ -807,8 +818,8 @@ static tg_status apply_plan(tg_readout* h, int target) {
   tg_status ps = plan_links(h, target);
   if (ps == TG_OK && hipMemcpy(h->d_kp, &h->kp, sizeof(KParams), hipMemcpyHostToDevice) != hipSuccess) ps = TG_ERR_HIP;
   if (ps == TG_OK) {
-    KernelFn kf = select_kernel(h->noise, h->xt, h->hy, 0, h->full);
-    KernelFn kf1 = select_kernel(h->noise, h->xt, h->hy, 1, h->full);
+    KernelFn kf = select_kernel(h->noise, kernel_xt(h), h->hy, 0, h->full);
+    KernelFn kf1 = select_kernel(h->noise, kernel_xt(h), h->hy, 1, h->full);
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
     (void)hipFuncSetAttribute((const void*)kf1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
   }
@@ -863,7 +874,7 @@ tg_status tg_readout_autotune(tg_readout* h, const tg_step_inputs* in, const tg_
     if (hipStreamSynchronize(st) != hipSuccess) { rs = TG_ERR_HIP; break; }
     if (plan_links(h, c) != TG_OK || h->lds > 160 * 1024) continue;
     if (hipMemcpy(h->d_kp, &h->kp, sizeof(KParams), hipMemcpyHostToDevice) != hipSuccess) { rs = TG_ERR_HIP; break; }
-    KernelFn kf = select_kernel(h->noise, h->xt, h->hy, in && in->obj_state ? 1 : 0, h->full);
+    KernelFn kf = select_kernel(h->noise, kernel_xt(h), h->hy, in && in->obj_state ? 1 : 0, h->full);
     (void)hipFuncSetAttribute((const void*)kf, hipFuncAttributeMaxDynamicSharedMemorySize, (int)h->lds);
     if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
     rs = tg_readout_rollout(h, in, out, n_steps, hip_stream);           // warm-up

@@ -262,3 +262,19 @@ def test_fixed_work_plans_keep_parity(torch_cuda, plan):
     ref = oracle_ref(sc, inp)
     parity.compare(g, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
                    link_offset=sc.layout.link_offset)
+
+
+def test_dense_crosstalk_of_a_large_link(torch_cuda):
+    """A 300-taxel link: 19 x 19 A tiles (185 KB) do not fit in LDS beside the rest, so the
+    kernel reads them from L2 each step, and K runs past 8 tiles; a 40-taxel link shares the
+    launch.  Same bar as the other noisy parity tests."""
+    torch = torch_cuda
+    import dataclasses
+    sc = synth.make_scene("c3", num_envs=6, num_steps=3)
+    sc = dataclasses.replace(sc, layout=synth.make_layout([300, 40]))
+    inp = synth.make_inputs(sc)
+    g = run_gpu(sc, inp)
+    ref = oracle_ref(sc, inp)
+    info = parity.compare(g, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
+                          link_offset=sc.layout.link_offset)
+    print(info)
