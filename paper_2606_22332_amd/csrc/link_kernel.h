@@ -47,9 +47,12 @@ __device__ __forceinline__ Pose pose_from13(const float* v) {
 
 // Outputs are written once and never read back by the kernel: non-temporal stores, so that the
 // output stream does not evict the grid bricks the gathers reuse from L2.
-__device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
-// Store through a uniform base and a per-lane 32-bit byte offset.
-__device__ __forceinline__ void store_at(float* base, uint32_t off4, float v) { store_nt((float*)((char*)base + off4), v); }
+// Non-temporal store through a uniform base (SGPR pair) and a per-lane 32-bit byte offset: the
+// scalar-base form of the vector store, so no per-lane 64-bit address is formed.  (Outputs are
+// never read by the kernel, so the store needs no ordering against its other memory accesses.)
+__device__ __forceinline__ void store_at(float* base, uint32_t off4, float v) {
+  asm volatile("global_store_dword %0, %1, %2 nt" : : "v"(off4), "v"(v), "s"(base));
+}
 
 // Two FP32 values rounded to BF16 (nearest even), packed low, high (one v_cvt_pk_bf16_f32).
 __device__ __forceinline__ uint32_t bf16_pack2(float lo, float hi) {
@@ -112,15 +115,12 @@ __device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* P, int n
     const float* v = P + ch * ngroups + el * gpe;
     float acc = 0.f;
     for (int g = 0; g < gpe; ++g) acc += v[g];
-    const int64_t col = (int64_t)l * p.E + e;
-    if (ch < 6) {
-      store_nt(out + ch * EL + col, acc);
-    } else if (ch == 6) {
-      store_nt(out + 6 * EL + col, acc);
-      store_nt(out + 7 * EL + col, acc > 2.5f ? 1.f : 0.f);
-    } else {
-      store_nt(out + (ch + 1) * EL + col, 1.0e4f * acc);
-    }
+    // byte offsets from the step's base: 11 * E * L * 4 fits 32 bits (checked at create)
+    const uint32_t col = (uint32_t)l * (uint32_t)p.E + (uint32_t)e;
+    const uint32_t el4 = (uint32_t)EL * 4u;
+    const uint32_t o = (uint32_t)(ch < 7 ? ch : ch + 1) * el4 + col * 4u;
+    store_at(out, o, ch < 7 ? acc : 1.0e4f * acc);
+    if (ch == 6) store_at(out, o + el4, acc > 2.5f ? 1.f : 0.f);
   }
 }
 
@@ -341,12 +341,13 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
       for (int c = 0; c < 6; ++c) XZ[c * nthr + tid] = z[c];
     }
     if (NOISE && XT >= 2 && act) {
-      uint16_t* bt = (uint16_t*)(smem + Ld.bt);
+      const int kp = li.kp;
+      uint16_t* brow = (uint16_t*)(smem + Ld.bt) + 6 * el * kp + k;   // column 6 el + c at c * kp
 #pragma unroll
       for (int c = 0; c < 6; c += 2) {
         const uint32_t w = bf16_pack2(z[c], z[c + 1]);
-        bt[(6 * el + c) * li.kp + k] = (uint16_t)(w & 0xffffu);
-        bt[(6 * el + c + 1) * li.kp + k] = (uint16_t)(w >> 16);
+        brow[c * kp] = (uint16_t)(w & 0xffffu);
+        brow[(c + 1) * kp] = (uint16_t)(w >> 16);
       }
     }
     if (!NOISE && pre && pf_off != -1) RAW[(par ^ 1) * nraw + tid] = rv;   // the other parity is free
@@ -417,9 +418,10 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
           zt[c] = acc;
         }
       } else if (XT >= 2) {
-        const float* dt = (const float*)(smem + Ld.dt);
+        const int kpd = li.kpd;
+        const float* drow = (const float*)(smem + Ld.dt) + 6 * el * kpd + k;   // row 6 el + c at c * kpd
 #pragma unroll
-        for (int c = 0; c < 6; ++c) zt[c] = act ? dt[(6 * el + c) * li.kpd + k] : 0.f;
+        for (int c = 0; c < 6; ++c) zt[c] = act ? drow[c * kpd] : 0.f;
       } else {
 #pragma unroll
         for (int c = 0; c < 6; ++c) zt[c] = z[c];

@@ -68,6 +68,12 @@ __device__ __forceinline__ float lerpf(float t, float a, float b) { return fmaf(
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds, two 32x32->64 products per round, key bumped
 // by the Weyl constants between rounds.
 // ---------------------------------------------------------------------------------------------
+// a ^ b ^ k in one v_bitop3_b32 (truth table 0x96 = three-way xor; k uniform, in an SGPR)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
 __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2, uint32_t& c3, uint32_t k0,
                                               uint32_t k1) {
 #pragma unroll
@@ -76,8 +82,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
     const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
     const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    const uint32_t n0 = xor3(hi1, c1, k0);
+    const uint32_t n2 = xor3(hi0, c3, k1);
     c0 = n0;
     c1 = lo1;
     c2 = n2;

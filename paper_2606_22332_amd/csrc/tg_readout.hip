@@ -324,6 +324,8 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
   if ((om & TG_OUT_NOISY) && !noise) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "noisy outputs need noise");
   if ((int64_t)E * T * 4 > (int64_t)0xffffffffLL)
     return fail(nullptr, TG_ERR_UNSUPPORTED, "num_envs * num_taxels * 4 must fit 32 bits (shard the envs)");
+  if ((int64_t)E * L * 11 * 4 > (int64_t)0xffffffffLL)
+    return fail(nullptr, TG_ERR_UNSUPPORTED, "num_envs * num_links * 44 must fit 32 bits (shard the envs)");
   if (cfg->sdf_mode != 0 && cfg->sdf_mode != 1) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "sdf_mode must be 0 or 1");
   if (cfg->sdf_mode == 1) {
     if (noise) return fail(nullptr, TG_ERR_UNSUPPORTED, "the neural SDF backend computes the clean readout only");
