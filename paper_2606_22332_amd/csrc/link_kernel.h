@@ -259,8 +259,8 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
     uint32_t* bt = (uint32_t*)(smem + Ld.bt);
     for (int i = tid; i < (li.nt * 16 * li.kp) / 2; i += nthr) bt[i] = 0u;
     if (XT == 2) {   // the link's A fragments, read from LDS at every step
-      uint2* af = (uint2*)(smem + Ld.afr);
-      const uint2* src = p.xt_afrag + (int64_t)li.afrag_off * 64;
+      uint4* af = (uint4*)(smem + Ld.afr);
+      const uint4* src = p.xt_afrag + (int64_t)li.afrag_off * 64;
       for (int i = tid; i < li.mt * li.kt * 64; i += nthr) af[i] = src[i];
     }
   }
@@ -367,38 +367,47 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
         const int ncols = 6 * envs;
         const int G = nwaves >= li.mt ? nwaves / li.mt : 1;
         for (int mt = wave % li.mt; mt < li.mt && wave < G * li.mt; mt += nwaves) {
-          const uint2* arow = p.xt_afrag + ((int64_t)li.afrag_off + (int64_t)mt * li.kt) * 64 + lane;
-          const uint2* lrow = (const uint2*)(smem + Ld.afr) + mt * li.kt * 64 + lane;
-          const uint2* asrc = XT == 2 ? lrow : arow;
-          uint2 afr[8];
+          const uint4* arow = p.xt_afrag + ((int64_t)li.afrag_off + (int64_t)mt * li.kt) * 64 + lane;
+          const uint4* lrow = (const uint4*)(smem + Ld.afr) + mt * li.kt * 64 + lane;
+          const uint4* asrc = XT == 2 ? lrow : arow;
+          uint4 afr[4];   // K tiles 0..3 (links of up to 128 taxels) stay in registers
 #pragma unroll
-          for (int kt = 0; kt < 8; ++kt) afr[kt] = kt < li.kt ? asrc[kt * 64] : make_uint2(0u, 0u);
-          for (int nt = (nwaves >= li.mt ? wave / li.mt : 0); nt < li.nt; nt += G) {
-            const int col = nt * 16 + (lane & 15);
-            const uint16_t* bcol = bt + col * li.kp + 4 * (lane >> 4);
-            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+          for (int kt = 0; kt < 4; ++kt) afr[kt] = kt < li.kt ? asrc[kt * 64] : make_uint4(0u, 0u, 0u, 0u);
+          // two N tiles per pass: independent accumulator chains interleave on the matrix core
+          for (int nt = (nwaves >= li.mt ? wave / li.mt : 0); nt < li.nt; nt += 2 * G) {
+            const int nt1 = nt + G;
+            const bool two = nt1 < li.nt;
+            const int col0 = nt * 16 + (lane & 15), col1 = nt1 * 16 + (lane & 15);
+            const uint16_t* b0 = bt + col0 * li.kp + 8 * (lane >> 4);
+            const uint16_t* b1 = bt + (two ? col1 : col0) * li.kp + 8 * (lane >> 4);
+            f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kt = 0; kt < 8; ++kt) {
+            for (int kt = 0; kt < 4; ++kt) {
               if (kt < li.kt) {
-                const uint2 b = *(const uint2*)(bcol + 16 * kt);
-                bf16x4 av, bv;
-                __builtin_memcpy(&av, &afr[kt], 8);
-                __builtin_memcpy(&bv, &b, 8);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+                const bf16x8 a = __builtin_bit_cast(bf16x8, afr[kt]);
+                acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, *(const uint4*)(b0 + 32 * kt)),
+                                                              acc0, 0, 0, 0);
+                if (two)
+                  acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, *(const uint4*)(b1 + 32 * kt)),
+                                                                acc1, 0, 0, 0);
               }
             }
-            for (int kt = 8; kt < li.kt; ++kt) {   // links of more than 128 taxels
-              const uint2 a = asrc[kt * 64];
-              const uint2 b = *(const uint2*)(bcol + 16 * kt);
-              bf16x4 av, bv;
-              __builtin_memcpy(&av, &a, 8);
-              __builtin_memcpy(&bv, &b, 8);
-              acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+            for (int kt = 4; kt < li.kt; ++kt) {   // links of more than 128 taxels
+              const bf16x8 a = __builtin_bit_cast(bf16x8, asrc[kt * 64]);
+              acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, *(const uint4*)(b0 + 32 * kt)),
+                                                            acc0, 0, 0, 0);
+              if (two)
+                acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, *(const uint4*)(b1 + 32 * kt)),
+                                                              acc1, 0, 0, 0);
             }
-            if (col < ncols) {
-              const int m0 = 16 * mt + 4 * (lane >> 4);
+            const int m0 = 16 * mt + 4 * (lane >> 4);
+            if (col0 < ncols) {
 #pragma unroll
-              for (int r = 0; r < 4; ++r) dt[col * li.kpd + m0 + r] = acc[r];
+              for (int r = 0; r < 4; ++r) dt[col0 * li.kpd + m0 + r] = acc0[r];
+            }
+            if (two && col1 < ncols) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) dt[col1 * li.kpd + m0 + r] = acc1[r];
             }
           }
         }

@@ -23,7 +23,7 @@ struct LinkInfo {
   int32_t off, n;        // first taxel, taxel count
   int32_t envs;          // envs per block for this link
   int32_t nwin;          // 64-bit words spanned by [off, off+n)
-  int32_t mt, kt, nt;    // dense crosstalk: M tiles, K tiles (16 rows each), N tiles of 16 columns
+  int32_t mt, kt, nt;    // dense crosstalk: M tiles of 16 rows, K tiles of 32, N tiles of 16 columns
   int32_t kp, kpd;       // padded K stride (bf16 elements) of the B staging, of the result staging
   int32_t afrag_off;     // first A tile of this link in the fragment buffer
   int32_t np;            // lanes per env: n rounded up to a multiple of 8 (aligned 8-lane groups)
@@ -68,7 +68,7 @@ struct KParams {
   int32_t afr_lds;               // 1: the link's dense crosstalk A fragments staged in LDS
   LinkLds lds;
   // dense crosstalk (kind 2)
-  const uint2* xt_afrag;         // A fragments, 4 bf16 per lane, 64 lanes per 16x16 tile
+  const uint4* xt_afrag;         // A fragments, 8 bf16 per lane, 64 lanes per 16x32 tile
 };
 
 // Per-launch arguments (kernel arguments); everything fixed for a handle lives in a KParams

@@ -174,9 +174,9 @@ tg_status plan_links(tg_readout* h, int target) {
     li.envs = std::max(1, std::min(std::min(E, 36), target / li.np));
     li.nwin = li.n > 0 ? ((li.off + li.n - 1) >> 6) - (li.off >> 6) + 1 : 1;
     li.nt = (6 * li.envs + 15) / 16;
-    const int n16 = ((li.n + 15) / 16) * 16;
-    li.kp = n16 + 8;
-    li.kpd = n16 + 4;
+    const int n16 = ((li.n + 15) / 16) * 16, n32 = ((li.n + 31) / 32) * 32;
+    li.kp = n32 + 8;    // B staging column stride (bf16): K tiles of 32, 16-byte aligned columns
+    li.kpd = n16 + 4;   // result staging row stride (floats)
     nthr = std::max(nthr, ((li.envs * li.np + 63) / 64) * 64);
   }
   {  // the per-step input prefetch parks 14 scalars per env, one per lane
@@ -217,7 +217,7 @@ tg_status plan_links(tg_readout* h, int target) {
   // the dense crosstalk A fragments of the largest link, resident in LDS when they fit
   int64_t afr = 0;
   if (h->xt == 2)
-    for (int l = 0; l < L; ++l) afr = std::max<int64_t>(afr, (int64_t)h->links[l].mt * h->links[l].kt * 64 * 8);
+    for (int l = 0; l < L; ++l) afr = std::max<int64_t>(afr, (int64_t)h->links[l].mt * h->links[l].kt * 64 * 16);
   h->kp.afr_lds = (h->xt == 2 && afr > 0 && align16i(o + afr) <= 160 * 1024) ? 1 : 0;
   d.afr = (int32_t)o; o = align16i(o + (h->kp.afr_lds ? afr : 0));
   d.total = (int32_t)o;

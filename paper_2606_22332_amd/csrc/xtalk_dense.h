@@ -3,15 +3,18 @@
 // uneven taxel set of each link, G_l the row-L1-normalised Gaussian of link-frame distances).
 //
 // For a block of `envs` envs of one link the six F/T channels of every env form the columns
-// of Z_l (n_l x 6*envs); the block computes C_l Z_l with v_mfma_f32_16x16x16_bf16 (BF16
+// of Z_l (n_l x 6*envs); the block computes C_l Z_l with v_mfma_f32_16x16x32_bf16 (BF16
 // operands, FP32 accumulation).  C_l is rounded once on the host (FP64 -> FP32 -> BF16, ties to even)
 // and stored as ready-made A fragments; Z is rounded to BF16 by the lanes that own it and
-// staged in LDS with every link padded to a multiple of 16 rows (padding stays zero).
+// staged in LDS with every link padded to a multiple of 32 K rows (padding stays zero).
 //
-// MFMA 16x16x16 (bf16, "1k") lane layout, 64 lanes, 4 elements per lane:
-//   A: lane i holds A[i%16][4*(i/16) + r]        r = 0..3
-//   B: lane i holds B[4*(i/16) + r][i%16]
-//   D: lane i holds D[4*(i/16) + r][i%16]
+// MFMA 16x16x32 (bf16) lane layout, 64 lanes = 4 groups g of 16, 8 K slots per lane.  A and B
+// must give slot (g, j) the same K index, and nothing else is required of the mapping; here slot
+// (g, j) of K tile kt is k = 32 kt + 8 g + j, so a lane's B items are 8 consecutive bf16 of one
+// staged column (one 16-byte LDS read):
+//   A: lane i holds A[i%16][32 kt + 8 (i/16) + j]        j = 0..7
+//   B: lane i holds B[32 kt + 8 (i/16) + j][i%16]
+//   D: lane i holds D[4 (i/16) + r][i%16]                r = 0..3
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -25,11 +28,11 @@
 
 namespace tg {
 
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct XtDense {
-  uint2* afrag = nullptr;     // per link: [mt][kt][64 lanes] x 4 bf16
+  uint4* afrag = nullptr;     // per link: [mt][kt][64 lanes] x 8 bf16 (K tiles of 32)
   std::vector<void*> allocs;
 };
 
@@ -46,10 +49,10 @@ inline tg_status xt_dense_setup(XtDense& X, const tg_readout_config* cfg, LinkIn
   const int L = cfg->num_links;
   const int32_t* off = cfg->link_taxel_offset;
   const double chi = (double)cfg->noise.xtalk_chi, sg = (double)cfg->noise.xtalk_sigma;
-  std::vector<uint2> frag;
+  std::vector<uint4> frag;
   for (int l = 0; l < L; ++l) {
     const int a = off[l], n = off[l + 1] - a;
-    const int MT = (n + 15) / 16, KT = MT;
+    const int MT = (n + 15) / 16, KT = (n + 31) / 32;
     links[l].mt = MT;
     links[l].kt = KT;
     links[l].afrag_off = (int32_t)(frag.size() / 64);
@@ -71,18 +74,19 @@ inline tg_status xt_dense_setup(XtDense& X, const tg_readout_config* cfg, LinkIn
     for (int mt = 0; mt < MT; ++mt)
       for (int kt = 0; kt < KT; ++kt)
         for (int lane = 0; lane < 64; ++lane) {
-          uint16_t v[4];
-          for (int r = 0; r < 4; ++r) {
-            const int m = 16 * mt + lane % 16, k = 16 * kt + 4 * (lane / 16) + r;
-            v[r] = (m < n && k < n) ? host_bf16((float)C[(size_t)m * n + k]) : (uint16_t)0;
+          uint16_t v[8];
+          for (int j = 0; j < 8; ++j) {
+            const int m = 16 * mt + lane % 16, k = 32 * kt + 8 * (lane / 16) + j;
+            v[j] = (m < n && k < n) ? host_bf16((float)C[(size_t)m * n + k]) : (uint16_t)0;
           }
-          frag.push_back(make_uint2((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16)));
+          frag.push_back(make_uint4((uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16),
+                                    (uint32_t)v[4] | ((uint32_t)v[5] << 16), (uint32_t)v[6] | ((uint32_t)v[7] << 16)));
         }
   }
-  hipError_t e = hipMalloc(&X.afrag, std::max<size_t>(frag.size(), 1) * sizeof(uint2));
+  hipError_t e = hipMalloc(&X.afrag, std::max<size_t>(frag.size(), 1) * sizeof(uint4));
   if (e == hipSuccess) X.allocs.push_back(X.afrag);
   if (e == hipSuccess && !frag.empty())
-    e = hipMemcpy(X.afrag, frag.data(), frag.size() * sizeof(uint2), hipMemcpyHostToDevice);
+    e = hipMemcpy(X.afrag, frag.data(), frag.size() * sizeof(uint4), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     *err = std::string("dense crosstalk setup: ") + hipGetErrorString(e);
     return TG_ERR_OUT_OF_MEMORY;
