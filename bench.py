@@ -54,8 +54,10 @@ def cpu_baseline(sc, inp, target_s=12.0):
     oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision="f32", threads=threads,
                        want=("bit", "bit_noisy", "depth", "prox", "ft", "ft_noisy", "link_sums", "link_sums_noisy"))
     dt = time.perf_counter() - t0
-    if dt < target_s / 4:
-        n2 = int(min(sc.num_envs, max(n, n * target_s / max(dt, 1e-3))))
+    for _ in range(3):   # grow the sample until it takes about target_s (at most three rounds)
+        if dt >= target_s / 2 or n >= sc.num_envs:
+            break
+        n2 = int(min(sc.num_envs, max(n + 1, n * target_s / max(dt, 1e-3))))
         envs = np.linspace(0, sc.num_envs - 1, n2).astype(np.int64)
         t0 = time.perf_counter()
         oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision="f32", threads=threads,
