@@ -39,7 +39,7 @@ struct ThermalLaunch {
   float* temperature;          // [S][E][T] or null
 };
 
-__global__ __launch_bounds__(TH_THREADS) void tg_thermal_kernel(const ThermalLaunch q) {
+__global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const ThermalLaunch q) {
   constexpr int n = TH_N;
   const KParams& p = *q.kc;
   const ThermalParams& th = *q.th;
@@ -63,6 +63,17 @@ __global__ __launch_bounds__(TH_THREADS) void tg_thermal_kernel(const ThermalLau
   const float r = th.r, g = th.g, rf = th.rho_f, Tamb = th.T_amb;
   const int fxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
   const int myvox = y * n + x;
+  // The taxels over this column's top voxel, in taxel order, found once for the launch: up to four
+  // 16-bit indices packed in two registers (more than four: the per-step scan below).
+  uint32_t mine01 = 0u, mine23 = 0u;
+  int nmine = 0;
+  for (int k = 0; k < nl; ++k)
+    if (th.taxel_vox[jb + k] == myvox) {
+      if (nmine < 2) mine01 |= (uint32_t)k << (16 * nmine);
+      else if (nmine < 4) mine23 |= (uint32_t)k << (16 * (nmine - 2));
+      ++nmine;
+    }
+  const int tvox = tid < nl ? th.taxel_vox[jb + tid] : 0;   // top voxel of taxel tid (one per lane)
   for (int s = 0; s < q.n_steps; ++s) {
     // 1. poses of this step
     if (tid == 0) {
@@ -102,10 +113,18 @@ __global__ __launch_bounds__(TH_THREADS) void tg_thermal_kernel(const ThermalLau
     __syncthreads();
     // 3. contact coefficient of this column's top voxel, in taxel order
     float cv = 0.f;
-    for (int k = 0; k < nl; ++k)
-      if (th.taxel_vox[jb + k] == myvox) cv = cv + cd[k];
-    // 4. explicit step from the old values (exchange buffer and registers), into registers
-    float nc[n];
+    if (nmine <= 4) {
+      if (nmine > 0) cv = cv + cd[mine01 & 0xffffu];
+      if (nmine > 1) cv = cv + cd[mine01 >> 16];
+      if (nmine > 2) cv = cv + cd[mine23 & 0xffffu];
+      if (nmine > 3) cv = cv + cd[mine23 >> 16];
+    } else {
+      for (int k = 0; k < nl; ++k)
+        if (th.taxel_vox[jb + k] == myvox) cv = cv + cd[k];
+    }
+    // 4. explicit step from the old values (exchange buffer, and registers for z +- 1): the column
+    //    is updated in place from the bottom, with the old value below carried in `below`
+    float below = col[0];
 #pragma unroll
     for (int z = 0; z < n; ++z) {
       const float t = col[z];
@@ -113,22 +132,22 @@ __global__ __launch_bounds__(TH_THREADS) void tg_thermal_kernel(const ThermalLau
       const float xp = x < n - 1 ? ex[(z * n + y) * n + x + 1] : t;
       const float ym = y > 0 ? ex[(z * n + y - 1) * n + x] : t;
       const float yp = y < n - 1 ? ex[(z * n + y + 1) * n + x] : t;
-      const float zm = z > 0 ? col[z - 1] : t;
+      const float zm = z > 0 ? below : t;
       const float zp = z < n - 1 ? col[z + 1] : t;
       const float sum = ((xm + xp) + (ym + yp)) + (zm + zp);
       const int faces = fxy + (z == 0) + (z == n - 1);
       const float rfx = rf * (float)faces;
       float src = g + rfx * (Tamb - t);
       if (z == n - 1) src = src + cv * (Tobj - t);
-      nc[z] = t + (r * (sum - 6.0f * t) + src);
+      below = t;
+      col[z] = t + (r * (sum - 6.0f * t) + src);
     }
-#pragma unroll
-    for (int z = 0; z < n; ++z) col[z] = nc[z];
     top[myvox] = col[n - 1];
     __syncthreads();   // every read of ex and cd is done; top is complete
     if (q.temperature) {
       float* out = q.temperature + (int64_t)s * ET + (int64_t)e * T;
-      for (int k = tid; k < nl; k += TH_THREADS) out[jb + k] = top[th.taxel_vox[jb + k]];
+      if (tid < nl) out[jb + tid] = top[tvox];
+      for (int k = tid + TH_THREADS; k < nl; k += TH_THREADS) out[jb + k] = top[th.taxel_vox[jb + k]];
       if (f == 0)   // the first field's workgroup clears the taxels of the non-thermal links
         for (int j = tid; j < T; j += TH_THREADS)
           if (th.taxel_vox[j] < 0) out[j] = 0.f;
