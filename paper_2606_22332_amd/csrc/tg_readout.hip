@@ -796,6 +796,7 @@ static tg_status launch_rollout(tg_readout* h, const tg_step_inputs* in, const t
     t.obj_state = in->obj_state;
     t.obj_id = in->obj_id;
     t.temperature = out->temperature;
+    t.depth = out->depth;   // null unless the rollout writes depths
     hipLaunchKernelGGL(tg_thermal_kernel, dim3((unsigned)(h->E * h->thp.F)), dim3(TH_THREADS), 0,
                        (hipStream_t)hip_stream, t);
   }

@@ -37,6 +37,8 @@ struct ThermalLaunch {
   const float* obj_state;      // [S][13][E] or null
   const int32_t* obj_id;       // [S][E]
   float* temperature;          // [S][E][T] or null
+  const float* depth;          // [S][E][T] the rollout's clean depths (written by the readout
+                               // kernel before this launch), or null: recomputed here
 };
 
 __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const ThermalLaunch q) {
@@ -75,15 +77,15 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
     }
   const int tvox = tid < nl ? th.taxel_vox[jb + tid] : 0;   // top voxel of taxel tid (one per lane)
   for (int s = 0; s < q.n_steps; ++s) {
-    // 1. poses of this step
-    if (tid == 0) {
+    // 1. poses of this step (only to recompute the depths)
+    if (!q.depth && tid == 0) {
       const float* ls = q.link_state + (int64_t)s * 13 * EL;
       const int64_t c = (int64_t)e * L + l;
       lp.p[0] = ls[0 * EL + c]; lp.p[1] = ls[1 * EL + c]; lp.p[2] = ls[2 * EL + c];
       quat_to_R(ls[3 * EL + c], ls[4 * EL + c], ls[5 * EL + c], ls[6 * EL + c], lp.R);
       oid_s = q.obj_id[(int64_t)s * E + e];
     }
-    if (q.obj_state && tid == 1) {
+    if (!q.depth && q.obj_state && tid == 1) {
       const float* os = q.obj_state + (int64_t)s * 13 * E;
       op.p[0] = os[0 * E + e]; op.p[1] = os[1 * E + e]; op.p[2] = os[2 * E + e];
       quat_to_R(os[3 * E + e], os[4 * E + e], os[5 * E + e], os[6 * E + e], op.R);
@@ -91,7 +93,12 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
 #pragma unroll
     for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];
     __syncthreads();
-    // 2. clean depth of the link's taxels (same sequence as the readout)
+    // 2. clean depth of the link's taxels: the readout's own output when the rollout writes it,
+    //    else recomputed with the readout's FP32 sequence (the same value)
+    if (q.depth) {
+      const float* dep = q.depth + (int64_t)s * ET + (int64_t)e * T + jb;
+      for (int k = tid; k < nl; k += TH_THREADS) cd[k] = th.kappa * dep[k];
+    } else
     for (int k = tid; k < nl; k += TH_THREADS) {
       const int j = jb + k;
       const float4 ta = p.taxA[j];

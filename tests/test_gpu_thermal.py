@@ -1,9 +1,10 @@
 """Thermal fields fused into the readout rollout, against the CPU oracle through the C ABI.
 
-The kernel recomputes each thermal taxel's clean depth with the readout's FP32 sequence and applies
-the same written FP32 update as the oracle's float build, so both the per-step taxel temperatures
-and the fields after the rollout must equal the oracle bit for bit; the readout outputs of the same
-rollout keep their own parity bar.
+The kernel takes each thermal taxel's clean depth from the rollout's depth output, or recomputes it
+with the readout's FP32 sequence when the rollout does not write depths, and applies the same
+written FP32 update as the oracle's float build, so both the per-step taxel temperatures and the
+fields after the rollout must equal the oracle bit for bit on both paths; the readout outputs of
+the same rollout keep their own parity bar.
 """
 import numpy as np
 import pytest
@@ -34,15 +35,15 @@ def oracle_thermal(sc, inp, ref_depth, fields=None):
     return oracle.thermal_run(sc.thermal, sc.layout, ref_depth, fields=fields, precision="f32")
 
 
-@pytest.mark.parametrize("dt", [None, 0.05])
-def test_fields_and_taxel_temperatures_match_oracle(torch_cuda, dt):
+@pytest.mark.parametrize("dt,with_depth", [(None, True), (0.05, True), (0.05, False)])
+def test_fields_and_taxel_temperatures_match_oracle(torch_cuda, dt, with_depth):
     torch = torch_cuda
     from paper_2606_22332_amd import binding as B
     sc = c5_scene(dt=dt)
     inp = synth.make_inputs(sc)
     oid = inp.obj_id.copy(); oid[:, 2] = -1; inp.obj_id = oid          # an env without object
     S = inp.link_state.shape[0]
-    ro = B.Readout(sc)
+    ro = B.Readout(sc, B.OUT_ALL if with_depth else B.OUT_ALL & ~B.TG_OUT_DEPTH)
     ro.alloc_outputs(S)
     ro.rollout(B.to_device(inp), S)
     torch.cuda.synchronize()
