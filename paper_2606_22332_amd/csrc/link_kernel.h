@@ -1,27 +1,30 @@
 // The fused rollout kernel, organised by (link, env chunk) work items.
 //
 // A block owns one link l for `envs` consecutive environments and runs every step of the
-// launch for them: lane r <-> (env el = r / n_l, taxel k = r % n_l), about 512 readouts per
-// block whatever the link size (16..128 taxels), so uneven links waste few lanes, and two blocks
-// share a CU so that one block's memory latency hides behind the other's arithmetic.  Because a
-// block only ever sees one link, everything that couples taxels stays inside the block:
-//   - dense crosstalk C_l Z_l runs on MFMA with the six channels of all the block's envs as
-//     the N columns (N = 6 * envs, 24..120); the BF16 A fragments of every link (206 KB for the
-//     largest hand) stay resident in each XCD's L2 and a wave loads its M tile once per step;
+// launch for them: lane r <-> (env el = r / np, taxel k = r % np), np = n_l rounded up to a
+// multiple of 8, about 192..512 readouts per block whatever the link size, so uneven links waste
+// few lanes, and two blocks share a CU so that one block's memory latency hides behind the
+// other's arithmetic.  Because a block only ever sees one link, everything that couples taxels
+// stays inside the block:
+//   - dense crosstalk C_l Z_l runs on MFMA (16x16x32 BF16) with the six channels of all the
+//     block's envs as the N columns; the link's A fragments are staged in LDS for the launch
+//     (or read from L2 when they do not fit) and Z goes through an LDS staging area;
 //   - banded crosstalk reads in-link neighbours from LDS;
-//   - per-link sums (force/torque, contact count, agg_force) are reduced inside the block.
+//   - per-link sums (force/torque, contact count, agg_force) are reduced inside the block:
+//     DPP sums over aligned 8-lane groups (each group inside one env), then one lane per
+//     (channel, env) adds that env's group partials.
 // The noise state (drift, lag / Maxwell, Schmitt bit, dead flag, stuck value, gain) of each
 // readout lives in registers for the whole launch and touches HBM only at its ends.
 //
-// Per step: the scalars of the next step's link poses are prefetched (one or two per lane) and
-// parked in LDS before the step's last barrier; the loader lanes turn them into rotation
-// matrices at the start of the step.  Then compute the readout, store the clean outputs
-// (unit-stride runs of n_l floats per env), assemble contact bits in LDS windows and merge them
-// into the [E][ceil(T/64)] words (words shared with a neighbouring link are merged with atomic
-// and/or), then the noise chain and its outputs.
+// Per step (four barriers): the loader lanes build the rotation matrices from the pose scalars
+// that were prefetched one per lane during the previous step; then the readout (probe point,
+// gathers from the bricked grid, depth, contact, force/torque, proximity), its non-temporal
+// stores (unit-stride runs of n_l floats per env), contact bits into LDS windows and the clean
+// group sums; then the clean epilogue (bit words, link sums) and the crosstalk MFMA; then the
+// noise chain and its outputs; then the noisy epilogue.
 //
 // The physical block id is remapped so that each of the 8 XCDs works through a contiguous
-// range of items (neighbouring envs share objects, hence grid data in that XCD's L2).
+// range of items (neighbouring blocks share envs and their objects' bricks in that XCD's L2).
 #pragma once
 #include "readout_kernel.h"
 #include "xtalk_dense.h"

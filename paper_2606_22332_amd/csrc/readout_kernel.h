@@ -1,18 +1,8 @@
-// The fused tactile readout kernel: probe transform -> grid SDF -> depth, contact bit,
-// normal -> relative velocity -> force/torque and proximity -> noise model -> per-link
-// observations, for a block of whole environments, looping over steps inside the kernel.
-//
-// Thread mapping: one thread per (env, taxel) readout.  A block owns `eb` consecutive envs
-// (eb * T <= 1024 threads) for every step of the launch, so its noise state (drift, lag or
-// Maxwell, Schmitt bit, dead flag, stuck value, gain) lives in registers for the whole
-// rollout and touches HBM once at the start and once at the end.
-//
-// Per step the block stages the link poses of its envs in LDS (one thread per (env, link)
-// builds the rotation matrix), every thread gathers the 8 grid corners of its probe from
-// the object's grid (L2 / Infinity Cache resident), forms the outputs and writes them with
-// unit-stride stores.  Contact bits are assembled in LDS words and stored as 64-bit words.
-// Crosstalk (banded) reads in-link neighbours from LDS; dense crosstalk runs on MFMA.
-// Per-link sums are reduced from LDS by groups of 8 lanes.
+// Device pieces of the tactile readout shared by the rollout, neural and thermal kernels: the
+// parameter block (KParams) and launch arguments (KLaunch), the work-plan records (LinkInfo,
+// LinkLds), and one probe's readout as a fixed FP32 sequence: probe transform -> trilinear
+// lookup in the bricked grid SDF -> depth, contact bit, proximity -> for d > 0 the gradient
+// normal, relative velocity and force/torque (App. A).
 #pragma once
 #include "readout_device.h"
 
