@@ -191,6 +191,11 @@ def bench_c4(args) -> dict:
     nn_ = outs["neural"]["normal"].permute(0, 2, 3, 1)[c].cpu().numpy()
     both = (np.linalg.norm(nn_, axis=-1) > 0)
     ang = angle_deg(nn_[both], ng[both])
+    # the network supplies the normal only where |phi_nn| >= band, i.e. for a contact (phi < R_j)
+    # about where the probe is more than R_j + band deep; split the error there
+    deep = (dg[c].float().cpu().numpy() >= 2e-3)[both]
+    def q99(a):
+        return float(np.quantile(a, 0.99)) if a.size else 0.0
     readouts = E * T * S
     return {
         "metric": METRIC, "value": readouts / (res["neural"] * 1e-3), "unit": "taxel-readouts/s", "n_gpus": 1,
@@ -204,7 +209,8 @@ def bench_c4(args) -> dict:
         "depth_err_um": {"p50": float(np.quantile(derr, 0.5) * 1e6), "p99": float(np.quantile(derr, 0.99) * 1e6),
                          "max": float(derr.max() * 1e6), "contacts": int(c.sum().item())},
         "normal_err_deg": {"p50": float(np.quantile(ang, 0.5)), "p99": float(np.quantile(ang, 0.99)),
-                           "max": float(ang.max())},
+                           "max": float(ang.max()), "p99_depth_below_2mm": q99(ang[~deep]),
+                           "p99_depth_2mm_or_more": q99(ang[deep]), "fraction_2mm_or_more": float(deep.mean())},
         "training": {"steps": args.train_steps, "batch_per_object": 1 << 14, "samples_per_object": args.nsdf_samples,
                      "ms_total": train_ms, "ms_per_step": train_ms / args.train_steps,
                      "final_l1_um_median": float(np.median(loss_um)), "final_l1_um_max": float(loss_um.max())},

@@ -218,7 +218,9 @@ tg_status plan_links(tg_readout* h, int target) {
   int64_t afr = 0;
   if (h->xt == 2)
     for (int l = 0; l < L; ++l) afr = std::max<int64_t>(afr, (int64_t)h->links[l].mt * h->links[l].kt * 64 * 16);
-  h->kp.afr_lds = (h->xt == 2 && afr > 0 && align16i(o + afr) <= 160 * 1024) ? 1 : 0;
+  // stage them only when the CU still holds the 16 waves its VGPR budget allows (128 per lane)
+  const int64_t blocks_wanted = std::max(1, 16 / (nthr / 64));
+  h->kp.afr_lds = (h->xt == 2 && afr > 0 && align16i(o + afr) * blocks_wanted <= 160 * 1024) ? 1 : 0;
   d.afr = (int32_t)o; o = align16i(o + (h->kp.afr_lds ? afr : 0));
   d.total = (int32_t)o;
   h->lds = (size_t)o;
