@@ -154,7 +154,20 @@ def bench_c4(args) -> dict:
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
-    ns.train(P, m, v, rec, 0, args.train_steps, hp, loss=loss)
+    if args.lr_schedule == "cosine":
+        # Adam from lr 1e-3, decayed along a half cosine to 1e-5 over the run (in 20 constant
+        # pieces; the step counter, hence bias correction and minibatch draws, runs on)
+        pieces = 20
+        edges = np.linspace(0, args.train_steps, pieces + 1).astype(int)
+        for i in range(pieces):
+            n_i = int(edges[i + 1] - edges[i])
+            if n_i <= 0:
+                continue
+            lr_i = 1e-5 + 0.5 * (1e-3 - 1e-5) * (1.0 + np.cos(np.pi * (i + 0.5) / pieces))
+            hp_i = B.train_params(lr=float(lr_i), batch=1 << 14, seed=sc.geom_seed + 9)
+            ns.train(P, m, v, rec, int(edges[i]), n_i, hp_i, loss=loss[int(edges[i]):int(edges[i + 1])])
+    else:
+        ns.train(P, m, v, rec, 0, args.train_steps, hp, loss=loss)
     b.record()
     torch.cuda.synchronize()
     train_ms = a.elapsed_time(b)
@@ -212,6 +225,7 @@ def bench_c4(args) -> dict:
                            "max": float(ang.max()), "p99_depth_below_2mm": q99(ang[~deep]),
                            "p99_depth_2mm_or_more": q99(ang[deep]), "fraction_2mm_or_more": float(deep.mean())},
         "training": {"steps": args.train_steps, "batch_per_object": 1 << 14, "samples_per_object": args.nsdf_samples,
+                     "lr_schedule": args.lr_schedule,
                      "ms_total": train_ms, "ms_per_step": train_ms / args.train_steps,
                      "final_l1_um_median": float(np.median(loss_um)), "final_l1_um_max": float(loss_um.max())},
         "memory_MB": {"grids_fp32": n_obj * sc.grids[0].n ** 3 * 4 / 1e6,
@@ -236,6 +250,7 @@ def main():
     ap.add_argument("--workload", default="readout", choices=["readout", "c4"])
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--nsdf-samples", type=int, default=1 << 17)
+    ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"])
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
