@@ -5,9 +5,11 @@
 // takes NEU_ENVS consecutive envs of that order keeps one object's packed BF16 network image in
 // LDS and reloads it only when the object changes.  Inside an env, each wave takes groups of 64
 // consecutive taxels:
-//   tile phase   four MFMA tiles of 16 taxels: probe point -> x_hat -> network forward (all four
-//                lane groups hold the 16 samples); where a taxel needs a normal outside the
-//                band, the tile also runs the reverse pass for d out / d x_hat;
+//   probe        one taxel per lane: probe point, box test and x_hat;
+//   tile phase   four MFMA tiles of 16 taxels, x_hat taken from the owning lanes by shuffles:
+//                network forward (all four lane groups hold the 16 samples); where a taxel
+//                needs a normal outside the band, the tile also runs the reverse pass for
+//                d out / d x_hat;
 //   readout phase one taxel per lane (lane group g keeps tile g's results): the grid lookup
 //                where the point is far or |phi_nn| < band, then the same depth / normal /
 //                force / proximity sequence as the grid path; contact bits by wave ballot; link
@@ -93,9 +95,10 @@ __device__ __forceinline__ void pose_from_state(const float* st, int64_t col, in
   P.w[0] = st[10 * stride + col]; P.w[1] = st[11 * stride + col]; P.w[2] = st[12 * stride + col];
 }
 
-// LDS: image | SiLU table | link poses [L] | object pose | link sums [10][L]
+// Dynamic LDS: image | link poses [L] | object pose | link sums [10][L]; the SiLU table is a
+// static array of SILU_BYTES beside it.
 __host__ __device__ inline int neural_lds_bytes(int L) {
-  return nsdf::IMG_BYTES + nsdf::SILU_BYTES + (L + 1) * (int)sizeof(Pose) + 10 * L * 4 + 16;
+  return nsdf::IMG_BYTES + (L + 1) * (int)sizeof(Pose) + 10 * L * 4 + 16;
 }
 
 __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch qarg) {
@@ -113,10 +116,10 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
 #define NEU_REFRESH() asm volatile("" : "+s"(kc), "+s"(qp))
   const int E = p.E, L = p.L, T = p.T, W = p.W;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, s = lane & 15;
+  __shared__ __align__(16) uint16_t tab[SILU_ENTRIES];
   uint32_t* img = (uint32_t*)smem;
-  uint16_t* tab = (uint16_t*)(smem + IMG_BYTES);
   for (int i = tid; i < SILU_ENTRIES / 2; i += NEU_THREADS) ((uint32_t*)tab)[i] = ((const uint32_t*)q.silu)[i];
-  Pose* lpose = (Pose*)(smem + IMG_BYTES + SILU_BYTES);
+  Pose* lpose = (Pose*)(smem + IMG_BYTES);
   Pose* opose = lpose + L;
   float* sums = (float*)(opose + 1);
   const Img im = img_at(smem);
@@ -150,35 +153,42 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
 #pragma unroll 1
     for (int grp = wave; grp * 64 < T; grp += NEU_THREADS / 64) {
       const int j0 = grp * 64;
-      // ---- tile phase ----
+      // ---- probe of this lane's taxel j0 + lane (the tiles take theirs by lane shuffles) ----
+      const int j = j0 + lane;
+      const bool valid = j < T;
+      const float4 ta = valid ? p.taxA[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const float4 tb = valid ? p.taxB[j] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const int l = valid ? __float_as_int(tb.w) : 0;
+      const float xj[3] = {ta.x, ta.y, ta.z};
+      float qw[3] = {0.f, 0.f, 0.f}, qo[3] = {0.f, 0.f, 0.f}, xh[3] = {0.f, 0.f, 0.f};
+      bool far = false;
+      float rnet = -INFINITY;   // R_j where the network may have to supply this taxel's normal
+      if (has) {
+        probe_point(lpose[l], Op, xj, qw, qo);
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+          const float u = (qo[i] - gd.origin[i]) * gd.hinv;
+          far |= !(u >= 0.f && u <= gd.nm1);
+          xh[i] = (qo[i] - bx.centre[i]) * bx.half_inv;
+        }
+        if (valid && !far && ta.w > 0.f) rnet = ta.w;
+      }
+      // ---- tile phase: tile tt holds taxels j0 + 16 tt + (lane & 15) ----
       float my_phi = 0.f, my_g[3] = {0.f, 0.f, 0.f};
       if (has) {
 #pragma unroll 1
         for (int tt = 0; tt < 4; ++tt) {
-          const int j = j0 + 16 * tt + s;
-          const bool valid = j < T;
-          const float4 ta = valid ? p.taxA[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-          const float4 tb = valid ? p.taxB[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-          const int l = __float_as_int(tb.w);
-          const float xj[3] = {ta.x, ta.y, ta.z};
-          float qw[3], qo[3];
-          probe_point(lpose[valid ? l : 0], Op, xj, qw, qo);
-          bool far = false;
-          float xh[3];
-#pragma unroll
-          for (int i = 0; i < 3; ++i) {
-            const float u = (qo[i] - gd.origin[i]) * gd.hinv;
-            far |= !(u >= 0.f && u <= gd.nm1);
-            xh[i] = (qo[i] - bx.centre[i]) * bx.half_inv;
-          }
+          const int src = 16 * tt + s;
+          const float x0 = __shfl(xh[0], src), x1 = __shfl(xh[1], src), x2 = __shfl(xh[2], src);
+          const float rj = __shfl(rnet, src);
           uint32_t z[4][8];
           u32x4 pe[2];
           float a4[4][4];
-          const float out = forward_tile(im, lane, xh[0], xh[1], xh[2], z, pe, a4, tab);
+          const float out = forward_tile(im, lane, x0, x1, x2, z, pe, a4, tab);
           const float phi_nn = bx.half * out;
-          const bool need = valid && !far && ta.w > 0.f && !(fabsf(phi_nn) < q.band) && phi_nn < ta.w;
+          const bool need = !(fabsf(phi_nn) < q.band) && phi_nn < rj;
           float gx[3] = {0.f, 0.f, 0.f};
-          if (__any(need)) input_grad_tile(im, lane, xh[0], xh[1], xh[2], z, gx);
+          if (__any(need)) input_grad_tile(im, lane, x0, x1, x2, z, gx);
           if (g == tt) {
             my_phi = phi_nn;
             my_g[0] = gx[0]; my_g[1] = gx[1]; my_g[2] = gx[2];
@@ -186,25 +196,11 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
         }
       }
       // ---- readout phase: lane <-> taxel j0 + lane ----
-      const int j = j0 + lane;
-      const bool valid = j < T;
-      const float4 ta = valid ? p.taxA[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-      const float4 tb = valid ? p.taxB[j] : make_float4(0.f, 0.f, 0.f, 0.f);
-      const int l = valid ? __float_as_int(tb.w) : 0;
       TaxelOut o;
       taxel_out_clear(o);
       if (valid && has && ta.w > 0.f) {
         o.active = true;
         const Pose& Lp = lpose[l];
-        const float xj[3] = {ta.x, ta.y, ta.z};
-        float qw[3], qo[3];
-        probe_point(Lp, Op, xj, qw, qo);
-        bool far = false;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          const float u = (qo[i] - gd.origin[i]) * gd.hinv;
-          far |= !(u >= 0.f && u <= gd.nm1);
-        }
         if (far || fabsf(my_phi) < q.band) {
           GridHit h;
           grid_lookup(gd, p.grid_vals, qo, h);

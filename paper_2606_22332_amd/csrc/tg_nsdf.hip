@@ -94,8 +94,7 @@ constexpr int SROW = 20;                    // staging row: 16 samples + pad (u1
 constexpr int STAGE_U16 = 64 * SROW;        // one [64 feature][16 sample] buffer
 constexpr int STAGE_BYTES = 4 * 4 * 2 * STAGE_U16 * 2;   // [wave][layer][dz | act]
 constexpr int RED_FLOATS = 68;              // dw5[64], db5, loss
-constexpr int LDS_TAB = IMG_BYTES + STAGE_BYTES + RED_FLOATS * 4;   // SiLU table
-constexpr int LDS_FIT = LDS_TAB + SILU_BYTES;
+constexpr int LDS_FIT = IMG_BYTES + STAGE_BYTES + RED_FLOATS * 4;   // dynamic; the SiLU table is static
 
 __device__ __forceinline__ uint16_t* stage_buf(uint8_t* smem, int wave, int l, int which) {
   return (uint16_t*)(smem + IMG_BYTES) + ((wave * 4 + l) * 2 + which) * STAGE_U16;
@@ -241,7 +240,7 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
   float* Po = a.P + (size_t)o * NPARAM;
   const float4* So = a.samples + (size_t)o * a.n;
   for (int w = tid; w < IMG_WORDS; w += NT) ((uint32_t*)smem)[w] = image_word(Po, w);
-  uint16_t* tab = (uint16_t*)(smem + LDS_TAB);
+  __shared__ __align__(16) uint16_t tab[SILU_ENTRIES];
   for (int i = tid; i < SILU_ENTRIES / 2; i += NT) ((uint32_t*)tab)[i] = ((const uint32_t*)a.silu)[i];
   const Img im = img_at(smem);
   const int64_t per_step = TRAIN ? a.batch : a.n;
@@ -398,7 +397,7 @@ __global__ __launch_bounds__(NT) void nsdf_query_kernel(const uint32_t* __restri
   uint32_t* img = (uint32_t*)smem;
   const uint32_t* src = images + (size_t)o * IMG_WORDS;
   for (int w = tid; w < IMG_WORDS; w += NT) img[w] = src[w];
-  uint16_t* tab = (uint16_t*)(smem + IMG_BYTES);
+  __shared__ __align__(16) uint16_t tab[SILU_ENTRIES];
   for (int i = tid; i < SILU_ENTRIES / 2; i += NT) ((uint32_t*)tab)[i] = ((const uint32_t*)silu)[i];
   __syncthreads();
   const Img im = img_at(smem);
@@ -612,7 +611,7 @@ tg_status tg_nsdf_query(tg_nsdf* h, const float* params, const int64_t* offsets,
   if (max_count > 0) {
     const int64_t per_block = 4 * 16 * QUERY_TILES_PER_WAVE;
     const dim3 grid((unsigned)((max_count + per_block - 1) / per_block), (unsigned)h->n_obj);
-    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES + SILU_BYTES, s, h->d_img, offsets, xhat, out, grad,
+    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES, s, h->d_img, offsets, xhat, out, grad,
                        h->d_silu);
   }
   const hipError_t e = hipGetLastError();

@@ -333,7 +333,7 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     if (noise) return fail(nullptr, TG_ERR_UNSUPPORTED, "the neural SDF backend computes the clean readout only");
     if (!cfg->nsdf_params) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "sdf_mode 1 needs nsdf_params");
     if (!(cfg->nsdf_band >= 0.f)) return fail(nullptr, TG_ERR_INVALID_ARGUMENT, "nsdf_band must be >= 0");
-    if (neural_lds_bytes(L) > 160 * 1024) return fail(nullptr, TG_ERR_UNSUPPORTED, "too many links for the neural kernel");
+    if (neural_lds_bytes(L) + nsdf::SILU_BYTES > 160 * 1024) return fail(nullptr, TG_ERR_UNSUPPORTED, "too many links for the neural kernel");
   }
   std::vector<int32_t> taxel_vox;
   double th_r = 0, th_g = 0, th_rf = 0, th_kap = 0;
