@@ -77,6 +77,20 @@ __global__ void tg_clear_words_kernel(unsigned long long* a, unsigned long long*
   }
 }
 
+// Links without taxels get no work item; their per-link sums are zero (no force, no contact), so
+// their columns of the [S][11][L][E] sums are cleared before the launch.
+__global__ void tg_clear_empty_link_sums_kernel(float* a, float* b, const int32_t* empty, int n_empty, int64_t E,
+                                                int64_t L, int64_t total) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+    const int64_t e = i % E, r = i / E;
+    const int64_t m = r % n_empty, sc = r / n_empty;   // sc = step * 11 + channel
+    const int64_t o = sc * L * E + (int64_t)empty[m] * E + e;
+    if (a) a[o] = 0.f;
+    if (b) b[o] = 0.f;
+  }
+}
+
 // ------------------------------------------------------------------------------------------------
 // handle
 // ------------------------------------------------------------------------------------------------
@@ -88,6 +102,8 @@ struct tg_readout {
   std::vector<LinkInfo> links;
   LinkInfo* d_links = nullptr;
   int2* d_items = nullptr;
+  int32_t* d_empty = nullptr;   // links without taxels
+  int n_empty = 0;
   int xt = 0, hy = 0, noise = 0, full = 1;
   KParams kp{};
   KParams* d_kp = nullptr;   // device copy read by the kernels
@@ -441,6 +457,20 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     tg_readout_destroy(h);
     return fail(nullptr, TG_ERR_OUT_OF_MEMORY, std::string("hipMalloc: ") + hipGetErrorString(e));
   }
+  {
+    std::vector<int32_t> empty;
+    for (int l = 0; l < L; ++l)
+      if (cfg->link_taxel_offset[l + 1] == cfg->link_taxel_offset[l]) empty.push_back(l);
+    h->n_empty = (int)empty.size();
+    if (h->n_empty > 0) {
+      if ((e = dalloc(h, &h->d_empty, empty.size())) == hipSuccess)
+        e = hipMemcpy(h->d_empty, empty.data(), empty.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+      if (e != hipSuccess) {
+        tg_readout_destroy(h);
+        return fail(nullptr, TG_ERR_OUT_OF_MEMORY, std::string("empty-link list: ") + hipGetErrorString(e));
+      }
+    }
+  }
   float *dDrift = nullptr, *dHy = nullptr, *dHp = nullptr, *dStuck = nullptr, *dGain = nullptr;
   uint8_t *dSch = nullptr, *dDead = nullptr;
   if ((e = dalloc(h, &dDrift, 6 * ET)) != hipSuccess || (e = dalloc(h, &dHy, 6 * ET)) != hipSuccess ||
@@ -787,6 +817,12 @@ static tg_status launch_rollout(tg_readout* h, const tg_step_inputs* in, const t
     const int64_t blocks = std::min<int64_t>((nw + 255) / 256, 16384);
     hipLaunchKernelGGL(tg_clear_words_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, k.bits,
                        k.bits_noisy, nw);
+  }
+  if (h->n_empty > 0 && (k.link_sums || k.link_sums_noisy)) {
+    const int64_t total = (int64_t)n_steps * 11 * h->n_empty * h->E;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
+    hipLaunchKernelGGL(tg_clear_empty_link_sums_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream,
+                       k.link_sums, k.link_sums_noisy, h->d_empty, h->n_empty, (int64_t)h->E, (int64_t)h->L, total);
   }
   hipLaunchKernelGGL(kf, dim3(h->kp.n_items_pad), dim3(h->threads), h->lds, (hipStream_t)hip_stream, k);
   if (h->thermal) {

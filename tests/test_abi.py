@@ -71,3 +71,25 @@ def test_unstable_thermal_configuration_is_rejected_at_create():
     rc = lib.tg_readout_create(C.byref(cfg), C.byref(h))
     assert rc == 5 and not h.value             # TG_ERR_UNSTABLE
     assert b"stable" in lib.tg_readout_last_error(None)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+@pytest.mark.parametrize("field,value,status", [
+    ("num_envs", 0, 1),                     # sizes must be positive
+    ("num_taxels", 0, 1),
+    ("num_envs", 1 << 20, 4),               # E * T * 4 bytes past 2^32: shard the envs
+    ("abi_version", 99, 1),
+])
+def test_create_rejects_bad_sizes_on_the_host(field, value, status):
+    """Size and version errors are found on the host before any device call (here, where no
+    GPU exists, a call that got past them would fail differently)."""
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+    import ctypes as C
+    sc = synth.make_scene("c3", num_envs=4, num_steps=1)
+    lib = B.load()
+    keep = []
+    cfg = B.make_config(sc, B.OUT_ALL, keep)
+    setattr(cfg, field, value)
+    h = C.c_void_p()
+    assert lib.tg_readout_create(C.byref(cfg), C.byref(h)) == status and not h.value

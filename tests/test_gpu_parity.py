@@ -278,3 +278,43 @@ def test_dense_crosstalk_of_a_large_link(torch_cuda):
     info = parity.compare(g, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
                           link_offset=sc.layout.link_offset)
     print(info)
+
+
+def degenerate_layout(counts):
+    """Hand patches for the nonempty links, with empty links spliced in and every 17th taxel an
+    inactive filler (R_j = 0)."""
+    base = synth.make_layout([c for c in counts if c > 0])
+    off = np.zeros(len(counts) + 1, np.int32)
+    off[1:] = np.cumsum(counts)
+    rad = base.radius.copy()
+    rad[::17] = 0.0
+    return synth.Layout(off, base.pos, base.normal, rad)
+
+
+@pytest.mark.parametrize("cfg", ["c2", "c3"])
+def test_empty_single_and_word_crossing_links(torch_cuda, cfg):
+    """Degenerate layouts under banded (c2) and dense (c3) crosstalk: links without taxels (first,
+    middle and last), one-taxel links, links that cross 64-bit bit-word boundaries, inactive
+    fillers.  Every output element must be written on every step: the buffers start as NaN and
+    the bit words as all ones."""
+    torch = torch_cuda
+    import dataclasses
+    from paper_2606_22332_amd import binding as B
+    sc = synth.make_scene(cfg, num_envs=7, num_steps=3)
+    sc = dataclasses.replace(sc, layout=degenerate_layout([0, 1, 63, 0, 9, 64, 1, 0]))
+    inp = synth.make_inputs(sc)
+    ro = B.Readout(sc)
+    ro.alloc_outputs(3)
+    for v in ro.out.values():
+        v.fill_(-1 if v.dtype == torch.int64 else float("nan"))
+    ro.rollout(B.to_device(inp), 3)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in ro.out.items()}
+    ro.out = {}
+    ro.close()
+    ref = oracle_ref(sc, inp)
+    info = parity.compare(g, ref, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
+                          link_offset=sc.layout.link_offset)
+    for k in ("link_sums", "link_sums_noisy"):
+        assert np.all(g[k][:, :, :, [0, 3, 7]] == 0.0)
+    print(cfg, info)
