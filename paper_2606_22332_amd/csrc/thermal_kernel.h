@@ -65,6 +65,11 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
   const float r = th.r, g = th.g, rf = th.rho_f, Tamb = th.T_amb;
   const int fxy = (x == 0) + (x == n - 1) + (y == 0) + (y == n - 1);
   const int myvox = y * n + x;
+  // exchange-buffer slots of the four in-plane neighbours (at z = 0; + z n^2 for layer z); on a
+  // face the voxel's own slot, which holds its current value: the mirrored neighbour, with no
+  // per-voxel select
+  const int sxm = x > 0 ? myvox - 1 : myvox, sxp = x < n - 1 ? myvox + 1 : myvox;
+  const int sym = y > 0 ? myvox - n : myvox, syp = y < n - 1 ? myvox + n : myvox;
   // The taxels over this column's top voxel, in taxel order, found once for the launch: up to four
   // 16-bit indices packed in two registers (more than four: the per-step scan below).
   uint32_t mine01 = 0u, mine23 = 0u;
@@ -135,10 +140,8 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
 #pragma unroll
     for (int z = 0; z < n; ++z) {
       const float t = col[z];
-      const float xm = x > 0 ? ex[(z * n + y) * n + x - 1] : t;
-      const float xp = x < n - 1 ? ex[(z * n + y) * n + x + 1] : t;
-      const float ym = y > 0 ? ex[(z * n + y - 1) * n + x] : t;
-      const float yp = y < n - 1 ? ex[(z * n + y + 1) * n + x] : t;
+      const float* ez = ex + z * n * n;
+      const float xm = ez[sxm], xp = ez[sxp], ym = ez[sym], yp = ez[syp];
       const float zm = z > 0 ? below : t;
       const float zp = z < n - 1 ? col[z + 1] : t;
       const float sum = ((xm + xp) + (ym + yp)) + (zm + zp);
