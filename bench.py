@@ -176,7 +176,8 @@ def bench_c4(args) -> dict:
     loss_um = (final_loss * half * 1e6).cpu().numpy()
     ns.close()
     del rec
-    mask = B.TG_OUT_BITS | B.TG_OUT_DEPTH | B.TG_OUT_PROX | B.TG_OUT_FT | B.TG_OUT_NORMAL | B.TG_OUT_LINK_SUMS
+    mask = (B.TG_OUT_BITS | B.TG_OUT_DEPTH | B.TG_OUT_PROX | B.TG_OUT_FT | B.TG_OUT_NORMAL | B.TG_OUT_LINK_SUMS
+            | B.TG_OUT_SURFDIST)
     d = B.to_device(inp)
     res, outs = {}, {}
     for name, kw in (("grid", {}), ("neural", {"nsdf_params": P, "nsdf_band": 1e-3})):
@@ -193,7 +194,7 @@ def bench_c4(args) -> dict:
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))
         res[name] = float(np.median(ts))
-        outs[name] = {k: ro.out[k] for k in ("depth", "normal")}
+        outs[name] = {k: ro.out[k] for k in ("depth", "normal", "surfdist")}
         ro.out = {}
         ro.close()
     # error of the neural path against the grid path over taxels in contact on the grid path
@@ -207,6 +208,9 @@ def bench_c4(args) -> dict:
     # the network supplies the normal only where |phi_nn| >= band, i.e. for a contact (phi < R_j)
     # about where the probe is more than R_j + band deep; split the error there
     deep = (dg[c].float().cpu().numpy() >= 2e-3)[both]
+    # the network supplied phi (and, in contact, the normal) where its surface distance differs
+    # from the grid path's
+    net = (outs["neural"]["surfdist"] != outs["grid"]["surfdist"])[c].cpu().numpy()[both]
     def q99(a):
         return float(np.quantile(a, 0.99)) if a.size else 0.0
     readouts = E * T * S
@@ -223,7 +227,11 @@ def bench_c4(args) -> dict:
                          "max": float(derr.max() * 1e6), "contacts": int(c.sum().item())},
         "normal_err_deg": {"p50": float(np.quantile(ang, 0.5)), "p99": float(np.quantile(ang, 0.99)),
                            "max": float(ang.max()), "p99_depth_below_2mm": q99(ang[~deep]),
-                           "p99_depth_2mm_or_more": q99(ang[deep]), "fraction_2mm_or_more": float(deep.mean())},
+                           "p99_depth_2mm_or_more": q99(ang[deep]), "fraction_2mm_or_more": float(deep.mean()),
+                           "network_supplied": {"fraction": float(net.mean()),
+                                                "p50": float(np.quantile(ang[net], 0.5)) if net.any() else 0.0,
+                                                "p90": float(np.quantile(ang[net], 0.9)) if net.any() else 0.0,
+                                                "p99": q99(ang[net])}},
         "training": {"steps": args.train_steps, "batch_per_object": 1 << 14, "samples_per_object": args.nsdf_samples,
                      "lr_schedule": args.lr_schedule,
                      "ms_total": train_ms, "ms_per_step": train_ms / args.train_steps,

@@ -42,8 +42,8 @@ constexpr int IMG_BYTES = FWD_BYTES + BWD_BYTES + TAIL_FLOATS * 4;  // 65024
 constexpr int IMG_WORDS = IMG_BYTES / 4;
 // SiLU table: bf16(silu(z)) for every BF16 z with 2^-13 <= |z| < 2^7 (biased exponents
 // 114..133), at entry (sign << 12) | ((exponent - 114) << 7) | mantissa: the negative half
-// starts 4096 entries (8 KB) in, so that the sign bit lands on the byte offset with one shift
-// and mask; entries 2560..4095 are unused.  Outside that range the BF16 result has a closed
+// starts 4096 entries (8 KB) in, so that the sign bit becomes the offset with one shift;
+// entries 2560..4095 are unused.  Outside that range the BF16 result has a closed
 // form: z / 2 for smaller |z| (the z^2/4 term is below half an ulp), z itself for z >= 128 and
 // -0 for z <= -128 (the product underflows FP32).  Kernels keep the table in a static LDS array
 // (constant address, folded into the read's offset field).
@@ -216,37 +216,27 @@ __device__ __forceinline__ uint32_t silu_closed(uint32_t b) {
   }
   return (b >> 15) ? 0x8000u : b;   // |z| >= 128: z, or -0 below -128
 }
-typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-typedef short i16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void silu_words(const uint32_t z[8], uint32_t out[8], const uint16_t* tab) {
-  // Both halves of a word at once with packed 16-bit arithmetic: the clamped index t (< 2560,
-  // so doubling the word doubles both halves), and the sign bits (15, 31) shifted onto the 8 KB
-  // bit of each half's byte offset; any clamp shows as t != t_c.
-  constexpr unsigned short LO = SILU_E0 << 7, TOP = (SILU_NE << 7) - 1;
-  const uint8_t* tb = (const uint8_t*)tab;
-  uint32_t clamped = 0u;
+  uint32_t v[16];
+  bool any_out = false;
 #pragma unroll
-  for (int w = 0; w < 8; ++w) {
-    const uint32_t b = z[w];
-    const u16x2 t = __builtin_bit_cast(u16x2, b & 0x7fff7fffu) - (u16x2){LO, LO};
-    const u16x2 tc = __builtin_elementwise_min(t, (u16x2){TOP, TOP});
-    clamped |= __builtin_bit_cast(uint32_t, t) ^ __builtin_bit_cast(uint32_t, tc);
-    const uint32_t off = (__builtin_bit_cast(uint32_t, tc) << 1) | ((b >> 2) & 0x20002000u);
-    const uint32_t lo = *(const unsigned short*)(tb + (off & 0xffffu));
-    const uint32_t hi = *(const unsigned short*)(tb + (off >> 16));
-    out[w] = lo | (hi << 16);
+  for (int i = 0; i < 16; ++i) {
+    const uint32_t b = (i & 1) ? (z[i >> 1] >> 16) : (z[i >> 1] & 0xffffu);
+    const uint32_t t = (b & 0x7fffu) - (uint32_t)(SILU_E0 << 7);
+    any_out |= t >= (uint32_t)(SILU_NE << 7);
+    const uint32_t idx = min(t, (uint32_t)(SILU_NE << 7) - 1u) + (b >> 15) * (uint32_t)SILU_NEG;
+    v[i] = tab[idx];
   }
-  if (__any(clamped != 0u)) {
+  if (__any(any_out)) {
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const uint32_t b = (i & 1) ? (z[i >> 1] >> 16) : (z[i >> 1] & 0xffffu);
       const uint32_t t = (b & 0x7fffu) - (uint32_t)(SILU_E0 << 7);
-      if (t >= (uint32_t)(SILU_NE << 7)) {
-        const uint32_t c = silu_closed(b);
-        out[i >> 1] = (i & 1) ? ((out[i >> 1] & 0xffffu) | (c << 16)) : ((out[i >> 1] & 0xffff0000u) | c);
-      }
+      if (t >= (uint32_t)(SILU_NE << 7)) v[i] = silu_closed(b);
     }
   }
+#pragma unroll
+  for (int w = 0; w < 8; ++w) out[w] = v[2 * w] | (v[2 * w + 1] << 16);
 }
 
 // Table path of a hidden layer: BF16 pre-activations (kept in z) and the next layer's BF16
