@@ -130,7 +130,9 @@ typedef struct {
 typedef struct {
   uint32_t abi_version;            /* TG_ABI_VERSION */
   int32_t num_envs, num_links, num_taxels, num_objects;
-  const int32_t* link_taxel_offset;/* host [num_links+1]; taxels sorted by link          */
+  const int32_t* link_taxel_offset;/* host [num_links+1]; taxels sorted by link; a link
+                                      may be empty (offset[l+1] == offset[l]): its link
+                                      sums are zero                                       */
   const float* taxel_pos;          /* host [num_taxels*3] link-frame x_j [m]              */
   const float* taxel_normal;       /* host [num_taxels*3] link-frame unit n_j             */
   const float* taxel_radius;       /* host [num_taxels] R_j [m]; 0 = inactive filler      */
