@@ -215,6 +215,15 @@ tg_status tg_readout_state_size(const tg_readout* h, size_t* bytes);
 tg_status tg_readout_get_state(tg_readout* h, void* dst_dev, size_t bytes, void* hip_stream);
 tg_status tg_readout_set_state(tg_readout* h, const void* src_dev, size_t bytes, void* hip_stream);
 
+/* Errors found on the device, where the host cannot check inputs without a synchronisation
+ * (the boundary's convention for device-resident values).  Waits for all device work, returns
+ * the accumulated flags in *device_error_flags and clears them:
+ *   TG_DEVERR_BAD_OBJECT_ID  an object id outside [-1, num_objects) was read; that env was read
+ *                            out as having no object (every output zero), as for id -1.
+ * TG_ERR_INVALID_ARGUMENT for a NULL handle or flags pointer. */
+#define TG_DEVERR_BAD_OBJECT_ID 1u
+tg_status tg_readout_poll_errors(tg_readout* h, uint32_t* device_error_flags);
+
 /* Kernel launch shape the handle uses (for profiling tools): envs per block and threads. */
 tg_status tg_readout_launch_shape(const tg_readout* h, int32_t* envs_per_block, int32_t* threads);
 

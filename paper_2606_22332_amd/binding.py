@@ -20,6 +20,7 @@ ABI_VERSION = 1
 TG_OUT_BITS, TG_OUT_DEPTH, TG_OUT_PROX, TG_OUT_FT = 1, 2, 4, 8
 TG_OUT_NOISY, TG_OUT_NORMAL, TG_OUT_SURFDIST, TG_OUT_LINK_SUMS = 16, 32, 64, 128
 TG_OUT_TEMP = 256
+TG_DEVERR_BAD_OBJECT_ID = 1  # device error flag: an object id outside [-1, num_objects) was read
 OUT_ALL = 255                 # every readout output (TG_OUT_TEMP is added when the scene has fields)
 NSDF_NUM_PARAMS = 15681
 
@@ -90,6 +91,7 @@ def load() -> C.CDLL:
         "tg_readout_get_state": ([P, P, C.c_size_t, P], C.c_int),
         "tg_readout_set_state": ([P, P, C.c_size_t, P], C.c_int),
         "tg_readout_launch_shape": ([P, P, P], C.c_int),
+        "tg_readout_poll_errors": ([P, P], C.c_int),
         "tg_readout_set_graph": ([P, C.c_int32], C.c_int),
         "tg_readout_autotune": ([P, P, P, C.c_int32, P, P, P], C.c_int),
         "tg_readout_set_work_plan": ([P, C.c_int32], C.c_int),
@@ -227,6 +229,12 @@ class Readout:
             self.close()
         except Exception:
             pass
+
+    def poll_errors(self) -> int:
+        """Device error flags since the last poll (TG_DEVERR_*); waits for the device."""
+        f = C.c_uint32()
+        _check(self.lib, self.h, self.lib.tg_readout_poll_errors(self.h, C.byref(f)), "poll_errors")
+        return f.value
 
     def launch_shape(self):
         eb, th = C.c_int32(), C.c_int32()

@@ -286,7 +286,9 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
 #pragma unroll
       for (int c = 0; c < 13; ++c) pv[c] = rw[c * envs + tid];
       lp[tid] = pose_from13(pv);
-      oi[tid] = __float_as_int(rw[13 * envs + tid]);
+      const int oid = __float_as_int(rw[13 * envs + tid]);
+      oi[tid] = oid;
+      check_object_id(p.err, oid, p.n_obj);
       if (OBJ) {
         load_pose13(q.obj_state + (int64_t)s * 13 * p.E, p.E, e0 + tid, pv);
         op[tid] = pose_from13(pv);

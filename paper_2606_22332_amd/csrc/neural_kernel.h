@@ -133,6 +133,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
     const int e = q.order[idx];
     const int oid = q.obj_id[e];
     const bool has = oid >= 0 && oid < p.n_obj;
+    if (tid == 0) check_object_id(p.err, oid, p.n_obj);
     __syncthreads();                                       // LDS of the previous env is free
     if (has && oid != loaded) {
       const uint4* src = (const uint4*)(q.images + (size_t)oid * IMG_WORDS);

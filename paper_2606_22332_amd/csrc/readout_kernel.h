@@ -59,7 +59,17 @@ struct KParams {
   LinkLds lds;
   // dense crosstalk (kind 2)
   const uint4* xt_afrag;         // A fragments, 8 bf16 per lane, 64 lanes per 16x32 tile
+  // device error word, read and cleared by the host: bit 0 = an object id outside
+  // [-1, n_obj) was seen (that env was read out as having no object)
+  uint32_t* err;
 };
+
+constexpr uint32_t DEVERR_BAD_OBJECT_ID = 1u;   // TG_DEVERR_BAD_OBJECT_ID of the C header
+
+// Flag an object id outside [-1, n_obj) in the device error word.
+__device__ __forceinline__ void check_object_id(uint32_t* err, int oid, int n_obj) {
+  if (oid < -1 || oid >= n_obj) atomicOr(err, DEVERR_BAD_OBJECT_ID);
+}
 
 // Per-launch arguments (kernel arguments); everything fixed for a handle lives in a KParams
 // copy in device memory that the kernel reads through an opaque pointer.

@@ -104,6 +104,7 @@ struct tg_readout {
   int2* d_items = nullptr;
   int32_t* d_empty = nullptr;   // links without taxels
   int n_empty = 0;
+  uint32_t* d_err = nullptr;    // device error word (KParams::err)
   int xt = 0, hy = 0, noise = 0, full = 1;
   KParams kp{};
   KParams* d_kp = nullptr;   // device copy read by the kernels
@@ -562,7 +563,10 @@ tg_status tg_readout_create(const tg_readout_config* cfg, tg_readout** out) {
     tg_readout_destroy(h);
     return fail(nullptr, TG_ERR_UNSUPPORTED, "LDS footprint exceeds 160 KiB");
   }
-  e = dalloc(h, &h->d_kp, 1);
+  e = dalloc(h, &h->d_err, 1);
+  if (e == hipSuccess) e = hipMemset(h->d_err, 0, sizeof(uint32_t));
+  h->kp.err = h->d_err;
+  if (e == hipSuccess) e = dalloc(h, &h->d_kp, 1);
   if (e == hipSuccess) e = hipMemcpy(h->d_kp, &h->kp, sizeof(KParams), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     tg_readout_destroy(h);
@@ -976,6 +980,19 @@ tg_status tg_readout_get_state(tg_readout* h, void* dst_dev, size_t bytes, void*
 }
 tg_status tg_readout_set_state(tg_readout* h, const void* src_dev, size_t bytes, void* hip_stream) {
   return copy_state(h, const_cast<void*>(src_dev), bytes, false, hip_stream);
+}
+
+static_assert(DEVERR_BAD_OBJECT_ID == TG_DEVERR_BAD_OBJECT_ID, "device error bits match the C header");
+
+tg_status tg_readout_poll_errors(tg_readout* h, uint32_t* device_error_flags) {
+  if (!h || !device_error_flags) return fail(h, TG_ERR_INVALID_ARGUMENT, "NULL handle or flags");
+  uint32_t v = 0;
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(&v, h->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost);
+  if (e == hipSuccess) e = hipMemset(h->d_err, 0, sizeof(uint32_t));
+  if (e != hipSuccess) return fail(h, TG_ERR_HIP, std::string("poll_errors: ") + hipGetErrorString(e));
+  *device_error_flags = v;
+  return TG_OK;
 }
 
 tg_status tg_readout_launch_shape(const tg_readout* h, int32_t* envs_per_block, int32_t* threads) {

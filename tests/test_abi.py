@@ -47,6 +47,9 @@ def test_status_strings_and_null_handling():
     assert lib.tg_readout_create(None, None) == 1          # rejected on the host, nothing launched
     lib.tg_readout_step.argtypes = [ctypes.c_void_p] * 4
     assert lib.tg_readout_step(None, None, None, None) == 1
+    lib.tg_readout_poll_errors.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    flags = ctypes.c_uint32(7)
+    assert lib.tg_readout_poll_errors(None, ctypes.byref(flags)) == 1 and flags.value == 7
 
 
 def test_binding_raises_without_library(tmp_path, monkeypatch):

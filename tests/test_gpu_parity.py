@@ -167,6 +167,35 @@ def test_object_id_edge_cases(torch_cuda):
     assert not g["depth"][:, :2].any()
 
 
+@pytest.mark.parametrize("neural", [False, True])
+def test_poll_errors_reports_bad_object_ids(torch_cuda, neural):
+    """The device error word: an id outside [-1, num_objects) sets TG_DEVERR_BAD_OBJECT_ID (its env
+    reads as 'no object'); -1 alone sets nothing; a poll clears the word."""
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    sc = synth.make_scene("c2", num_envs=6, num_steps=2)
+    kw = {}
+    if neural:
+        sc.noise = synth.NoiseParams(enabled=False, seed=sc.noise.seed)
+        kw = dict(nsdf_params=torch.from_numpy(synth.nsdf_init(len(sc.grids), 3)).cuda(), nsdf_band=1e-3)
+    mask = B.TG_OUT_DEPTH | B.TG_OUT_BITS
+    ro = B.Readout(sc, mask, **kw)
+    ro.alloc_outputs(2)
+    inp = synth.make_inputs(sc)
+    inp.obj_id[:, 0] = -1
+    ro.rollout(B.to_device(inp), 2)
+    assert ro.poll_errors() == 0
+    for bad in (len(sc.grids), -2):
+        inp.obj_id[1, 3] = bad
+        ro.rollout(B.to_device(inp), 2)
+        assert ro.poll_errors() == B.TG_DEVERR_BAD_OBJECT_ID
+        assert ro.poll_errors() == 0                 # cleared by the poll
+        assert not ro.out["depth"][1, 3].any()
+        inp.obj_id[1, 3] = 0
+    ro.out = {}
+    ro.close()
+
+
 def test_c3_full_size_sampled(torch_cuda):
     """The benchmark's launch: 20480 envs x 1024 taxels x 64 steps in one rollout; sampled envs
     are recomputed by the oracle over every step."""
