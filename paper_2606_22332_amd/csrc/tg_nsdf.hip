@@ -93,7 +93,8 @@ namespace {
 constexpr int SROW = 20;                    // staging row: 16 samples + pad (u16), 40 bytes
 constexpr int STAGE_U16 = 64 * SROW;        // one [64 feature][16 sample] buffer
 constexpr int STAGE_BYTES = 4 * 4 * 2 * STAGE_U16 * 2;   // [wave][layer][dz | act]
-constexpr int RED_FLOATS = 68;              // dw5[64], db5, loss
+constexpr int RED_FLOATS = 4 * 66 + 4;      // per wave: dw5[64], db5, loss; then the summed loss
+static_assert(B5_OFF == W5_OFF + 64, "db5 follows dw5 in the parameter vector");
 constexpr int LDS_FIT = IMG_BYTES + STAGE_BYTES + RED_FLOATS * 4;   // dynamic; the SiLU table is static
 
 __device__ __forceinline__ uint16_t* stage_buf(uint8_t* smem, int wave, int l, int which) {
@@ -249,7 +250,6 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
   const int n_steps = TRAIN ? a.n_steps : 1;
   for (int it = 0; it < n_steps; ++it) {
     const int64_t step = a.step0 + 1 + it;
-    if (tid < RED_FLOATS) red[tid] = 0.f;
     __syncthreads();
     f32x4 acc[4][4];
     float dbp[4], dw5[4][4], db5 = 0.f, lossp = 0.f;
@@ -285,8 +285,6 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
     // Gradient of the step into LDS (the staging area is free now): owners write their layer,
     // the output layer is reduced over lanes and waves.
     float* Gl = (float*)(smem + IMG_BYTES);
-    if (tid < H + 1) Gl[W5_OFF + tid] = 0.f;
-    __syncthreads();
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -302,6 +300,10 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
       v += __shfl_xor(v, 32);
       if (g == 0) Gl[B_OFF[L] + 16 * m + s] = v;
     }
+    // Output layer and loss: each wave reduces its lanes and parks its partials (dw5, db5, loss)
+    // in its own slot; the four slots are then added in wave order, so the step's gradient does
+    // not depend on the order in which the waves arrive (training is bitwise repeatable).
+    float* part = red + wave * 66;
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
@@ -311,7 +313,7 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
         v += __shfl_xor(v, 4);
         v += __shfl_xor(v, 2);
         v += __shfl_xor(v, 1);
-        if (s == 0) atomicAdd(&Gl[W5_OFF + 16 * m + 4 * g + q], v);
+        if (s == 0) part[16 * m + 4 * g + q] = v;
       }
     {
       float v = db5, w = lossp;
@@ -321,15 +323,21 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
         w += __shfl_xor(w, k);
       }
       if (lane == 0) {
-        atomicAdd(&Gl[B5_OFF], v);
-        atomicAdd(&red[65], w);
+        part[64] = v;
+        part[65] = w;
       }
+    }
+    __syncthreads();
+    if (tid < 66) {
+      const float t = ((red[tid] + red[66 + tid]) + red[132 + tid]) + red[198 + tid];
+      if (tid < 65) Gl[W5_OFF + tid] = t;   // dw5[0..63], then db5 at B5_OFF = W5_OFF + 64
+      else red[264] = t;                    // loss
     }
     __syncthreads();
     if (!TRAIN) {
       float* G = a.grad + (size_t)o * NPARAM;
       for (int i = tid; i < NPARAM; i += NT) G[i] = Gl[i];
-      if (a.loss && tid == 0) a.loss[o] = red[65] * inv_n;
+      if (a.loss && tid == 0) a.loss[o] = red[264] * inv_n;
     } else {
       float* Mo = a.M + (size_t)o * NPARAM;
       float* Vo = a.V + (size_t)o * NPARAM;
@@ -365,7 +373,7 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
           tail[t] = p;
         }
       }
-      if (a.loss && tid == 0) a.loss[(size_t)it * a.n_obj + o] = red[65] * inv_n;
+      if (a.loss && tid == 0) a.loss[(size_t)it * a.n_obj + o] = red[264] * inv_n;
     }
     __syncthreads();
   }

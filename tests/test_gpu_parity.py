@@ -347,3 +347,63 @@ def test_empty_single_and_word_crossing_links(torch_cuda, cfg):
     for k in ("link_sums", "link_sums_noisy"):
         assert np.all(g[k][:, :, :, [0, 3, 7]] == 0.0)
     print(cfg, info)
+
+
+def test_nonfinite_and_nonunit_poses(torch_cuda):
+    """Host-forced bad inputs: NaN and Inf link positions, a quaternion of norm 2 (used as given,
+    no normalisation, on both sides) and a NaN angular velocity on a link in contact.  Both sides
+    run the same FP32 sequence, so they must agree on where NaN appears (a NaN probe point reads
+    as far: no contact and a NaN surface distance; a NaN velocity poisons that probe's force, its
+    crosstalk neighbours' noisy channels and their lag state) and, elsewhere, to the usual bars."""
+    sc = synth.make_scene("c2", num_envs=8, num_steps=3)
+    inp = synth.make_inputs(sc)
+    L = sc.layout.num_links
+    off = np.asarray(sc.layout.link_offset)
+    clean = oracle_ref(sc, inp)
+    e_c, j_c = np.argwhere(clean["depth"][1, 5:] > 0)[0]
+    e_c += 5
+    l_c = int(np.searchsorted(off, j_c, side="right") - 1)
+    ls = inp.link_state
+    ls[1, 0, 2 * L + 3] = np.nan                 # env 2, link 3: NaN position from step 1
+    ls[2, 1, 3 * L + 5] = np.inf                 # env 3, link 5: Inf position at step 2
+    ls[1, 3:7, 4 * L + 7] *= 2.0                 # env 4, link 7: quaternion of norm 2
+    ls[1, 10, e_c * L + l_c] = np.nan            # a NaN angular velocity on a link in contact
+    g = run_gpu(sc, inp)
+    r = oracle_ref(sc, inp)
+    nan_seen = inf_seen = 0
+    for k in ("depth", "prox", "surfdist", "ft", "ft_noisy", "normal", "link_sums", "link_sums_noisy"):
+        gn, rn = np.isnan(g[k]), np.isnan(r[k])
+        assert np.array_equal(gn, rn), f"{k}: NaN patterns differ at {np.argwhere(gn != rn)[:5]}"
+        gi, ri = np.isinf(g[k]), np.isinf(r[k])
+        assert np.array_equal(gi, ri) and np.array_equal(g[k][gi], r[k][ri]), f"{k}: infinities differ"
+        nan_seen += int(rn.sum())
+        inf_seen += int(ri.sum())
+        g[k] = np.where(gn | gi, 0.0, g[k]).astype(g[k].dtype)
+        r[k] = np.where(rn | ri, 0.0, r[k])
+    assert nan_seen > 0 and inf_seen > 0
+    assert np.isnan(clean["surfdist"]).sum() == 0
+    parity.compare(g, r, sc.layout.num_taxels, noisy=True, sigma=sc.noise.drift_sigma,
+                   link_offset=sc.layout.link_offset)
+
+
+def test_zero_step_rollout_is_a_no_op(torch_cuda):
+    """rollout with n_steps = 0 returns OK, writes nothing and leaves the state alone."""
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    sc = synth.make_scene("c2", num_envs=5, num_steps=2)
+    inp = synth.make_inputs(sc)
+    d = B.to_device(inp)
+    ro = B.Readout(sc)
+    ro.alloc_outputs(2)
+    for v in ro.out.values():
+        v.fill_(7)
+    st0 = torch.empty(ro.state_size(), dtype=torch.uint8, device="cuda")
+    st1 = torch.empty_like(st0)
+    ro.get_state(st0)
+    ro.rollout(d, 0)
+    ro.get_state(st1)
+    torch.cuda.synchronize()
+    assert all(bool((v == 7).all()) for v in ro.out.values())
+    assert torch.equal(st0, st1)
+    ro.out = {}
+    ro.close()
