@@ -85,3 +85,35 @@ def test_reset_and_state_roundtrip(torch_cuda):
     assert torch.equal(ro.thermal_fields(), f1)
     ro.out = {}
     ro.close()
+
+
+def test_c5_full_size_sampled(torch_cuda):
+    """The C5 benchmark's launch: 4096 envs x 200 taxels x 500 steps with five fields per env, one
+    rollout and the benchmark's output set; sampled envs (first, middle, last) recomputed by the
+    oracle over every step, readout and fields alike (fields and taxel temperatures bit-exact)."""
+    torch = torch_cuda
+    import dataclasses
+    from paper_2606_22332_amd import binding as B
+    sc = synth.make_scene("c5")
+    inp = synth.make_inputs(sc)
+    S, L = inp.link_state.shape[0], sc.layout.num_links
+    envs = np.array([0, 1, 2047, 4094, 4095])
+    mask = B.TG_OUT_BITS | B.TG_OUT_DEPTH | B.TG_OUT_PROX | B.TG_OUT_FT | B.TG_OUT_LINK_SUMS | B.TG_OUT_NOISY
+    ro = B.Readout(sc, mask)
+    ro.alloc_outputs(S)
+    ro.rollout(B.to_device(inp), S)
+    torch.cuda.synchronize()
+    idx = torch.as_tensor(envs, device="cuda")
+    g = {k: (v[:, idx] if v.ndim == 3 else v[:, :, idx]).cpu().numpy() for k, v in ro.out.items()}
+    fields = ro.thermal_fields()[idx].cpu().numpy()
+    ro.out = {}
+    ro.close()
+    torch.cuda.empty_cache()
+    ref = oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision="f32")
+    parity.compare({k: v for k, v in g.items() if k != "temperature"}, ref, sc.layout.num_taxels, noisy=True,
+                   sigma=sc.noise.drift_sigma, link_offset=sc.layout.link_offset)
+    th = dataclasses.replace(sc.thermal, T_obj=np.asarray(sc.thermal.T_obj)[envs])
+    f_ref, tt_ref, _ = oracle.thermal_run(th, sc.layout, ref["depth"], precision="f32")
+    assert np.array_equal(g["temperature"].astype(np.float64), tt_ref)
+    assert np.array_equal(fields.astype(np.float64), f_ref.astype(np.float64))
+    assert float(f_ref.max() - f_ref.min()) > 0.0
