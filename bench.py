@@ -90,6 +90,27 @@ KERNEL_SOURCES = ["readout_device.h", "readout_kernel.h", "link_kernel.h", "xtal
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "tg_link_kernel_c3_hbm_counters.txt")
 
 
+def copy_bandwidth(nbytes: int = 1 << 31, reps: int = 5) -> float:
+    """Achievable HBM bandwidth on this GPU (GB/s): a device-to-device copy of `nbytes`, counted
+    as read + write, best of `reps` after a warm-up."""
+    import torch
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (best * 1e-3) / 1e9
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -323,6 +344,7 @@ def main():
     value = readouts / (wall / args.steps)
     nbytes, _ = algorithmic_bytes(E, L, T, S, len(sc.grids), sc.grids[0].n, sc.noise.enabled, True)
     achieved = nbytes / (ms * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth()            # after the timed region
     eb, threads = ro.launch_shape()
     wkey = f"{sc.name}:E{E}:T{T}:S{S}:target{eb}:threads{threads}"
     rec = {
@@ -341,7 +363,8 @@ def main():
                      "kernel": "tg_link_kernel", "algorithmic_bytes_per_launch": nbytes,
                      "bytes_per_readout": nbytes / readouts, "kernel_ms_mean": ms,
                      "kernel_ms_min": float(np.min(kernel_ms)), "workload_key": wkey,
-                     "kernel_source_sha256": kernel_source_hash()},
+                     "kernel_source_sha256": kernel_source_hash(),
+                     "copy_gbs": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "input_gen_s": gen_s,
     }
     if not args.no_cpu_baseline:
