@@ -70,6 +70,44 @@ def cpu_baseline(sc, inp, target_s=12.0):
             "sample": f"{n} of {sc.num_envs} envs x {T} taxels x {S} steps ({dt:.1f} s, FP32 oracle)"}
 
 
+def fp64_error(sc, inp, out, envs):
+    """Error of the GPU rollout (fresh state at step 0) against the FP64 oracle on sampled envs:
+    contact-bit disagreement, depth and proximity absolute error, and per-3-vector relative error
+    of the clean and noisy force/torque (the noisy channel carries the BF16 crosstalk)."""
+    import oracle
+    from paper_2606_22332_amd import synth
+    L = sc.layout.num_links
+    ref = oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision="f64")
+    W = out["bits"].shape[-1]
+    res = {"envs": [int(e) for e in envs], "steps": int(inp.link_state.shape[0])}
+
+    def bits(words):
+        b = np.unpackbits(words.view(np.uint8).reshape(*words.shape[:-1], W * 8), axis=-1, bitorder="little")
+        return b[..., :sc.layout.num_taxels]
+
+    def rel3(g, r, floor):
+        # per 3-vector: |g - r|_inf / max(|r|_inf, floor), over vectors with |r|_inf > 1e-6
+        g = np.moveaxis(g.astype(np.float64), 1, -1).reshape(*g.shape[:1], g.shape[2], g.shape[3], 2, 3)
+        r = np.moveaxis(r, 1, -1).reshape(g.shape)
+        num = np.abs(g - r).max(-1)
+        den = np.abs(r).max(-1)
+        m = den > 1e-6
+        q = num[m] / np.maximum(den[m], floor)
+        return {"p99": float(np.quantile(q, 0.99)) if q.size else 0.0, "max": float(q.max()) if q.size else 0.0,
+                "abs_max": float(num.max()), "floor": floor}
+
+    res["bit_mismatch_fraction"] = float((bits(out["bits"]) != ref["bit"]).mean())
+    res["depth_max_abs_m"] = float(np.abs(out["depth"].astype(np.float64) - ref["depth"]).max())
+    res["prox_max_abs"] = float(np.abs(out["prox"].astype(np.float64) - ref["prox"]).max())
+    res["ft_rel"] = rel3(out["ft"], ref["ft"], 1e-6)
+    if "ft_noisy" in out:
+        res["bit_noisy_mismatch_fraction"] = float((bits(out["bits_noisy"]) != ref["bit_noisy"]).mean())
+        # floor: one step of drift (the noisy channel's own scale), so near-zero sums of crosstalk
+        # and drift do not read as large relative errors
+        res["ft_noisy_rel"] = rel3(out["ft_noisy"], ref["ft_noisy"], float(sc.noise.drift_sigma))
+    return res
+
+
 def copy_calibration(nbytes: int) -> None:
     """A plain device-to-device copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
     factor that turns those counters into bytes for the readout kernel."""
@@ -369,6 +407,15 @@ def main():
     }
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(sc, inp)
+        # error against the FP64 oracle: one more rollout from a fresh state at step 0, sampled envs
+        ro.reset(None, 0)
+        dinp.step0 = 0
+        ro.rollout(dinp, S)
+        torch.cuda.synchronize()
+        envs = np.unique(np.array([0, E // 3, (2 * E) // 3, E - 1]))
+        idx = torch.as_tensor(envs, device="cuda")
+        sub = {k: (v[:, idx] if v.ndim == 3 else v[:, :, idx]).cpu().numpy() for k, v in ro.out.items()}
+        rec["fp64_error"] = fp64_error(sc, inp, sub, envs)
     print(json.dumps(rec), flush=True)
     ro.close()
 
