@@ -189,8 +189,8 @@ def test_sphere_depth_closed_form_and_static_spring():
 
 
 def test_zero_force_when_probe_clear_of_surface():
-    """phi >= R_j: no depth, no contact, zero force and torque (the benchmark spec 'zero force when phi > 0',
-    phi read as the probe-sphere distance phi_g - R_j)."""
+    """phi >= R_j: no depth, no contact, zero force and torque (the zero-force property of a probe
+    clear of the surface, with phi read as the probe-sphere distance phi_g - R_j)."""
     sc = synth.make_scene("c2", num_envs=32, num_steps=4)
     inp = synth.make_inputs(sc)
     for prec in ("f32", "f64"):
