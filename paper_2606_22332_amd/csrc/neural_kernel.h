@@ -13,7 +13,8 @@
 //   readout phase one taxel per lane (lane group g keeps tile g's results): the grid lookup
 //                where the point is far or |phi_nn| < band, then the same depth / normal /
 //                force / proximity sequence as the grid path; contact bits by wave ballot; link
-//                sums by segmented wave reductions into LDS.
+//                sums by segmented wave reductions into a per-wave slot in LDS, the four slots
+//                added in wave order at the end of the env (bitwise repeatable).
 #pragma once
 #include "nsdf_device.h"
 #include "readout_kernel.h"
@@ -95,10 +96,15 @@ __device__ __forceinline__ void pose_from_state(const float* st, int64_t col, in
   P.w[0] = st[10 * stride + col]; P.w[1] = st[11 * stride + col]; P.w[2] = st[12 * stride + col];
 }
 
-// Dynamic LDS: image | link poses [L] | object pose | link sums [10][L]; the SiLU table is a
-// static array of SILU_BYTES beside it.
+// Per-wave link-sum slots [wave][10][L]: they live in the unused middle of the static SiLU table
+// (entries 2560..4095, 3 KB) when they fit there (L <= 19), else after the poses in dynamic LDS.
+static_assert(NEU_THREADS == 256, "the link sums add four wave slots");
+constexpr int NEU_HOLE_OFF = nsdf::SILU_NE * 128 * 2, NEU_HOLE_BYTES = nsdf::SILU_NEG * 2 - NEU_HOLE_OFF;
+__host__ __device__ inline bool neural_sums_in_hole(int L) { return 4 * 10 * L * 4 <= NEU_HOLE_BYTES; }
+// Dynamic LDS: image | link poses [L] | object pose | (link sums, when not in the table's hole);
+// the SiLU table is a static array of SILU_BYTES beside it.
 __host__ __device__ inline int neural_lds_bytes(int L) {
-  return nsdf::IMG_BYTES + (L + 1) * (int)sizeof(Pose) + 10 * L * 4 + 16;
+  return nsdf::IMG_BYTES + (L + 1) * (int)sizeof(Pose) + (neural_sums_in_hole(L) ? 0 : 4 * 10 * L * 4) + 16;
 }
 
 __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch qarg) {
@@ -121,7 +127,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
   for (int i = tid; i < SILU_ENTRIES / 2; i += NEU_THREADS) ((uint32_t*)tab)[i] = ((const uint32_t*)q.silu)[i];
   Pose* lpose = (Pose*)(smem + IMG_BYTES);
   Pose* opose = lpose + L;
-  float* sums = (float*)(opose + 1);
+  float* sums = neural_sums_in_hole(L) ? (float*)((uint8_t*)tab + NEU_HOLE_OFF) : (float*)(opose + 1);
   const Img im = img_at(smem);
   const int64_t EL = (int64_t)E * L, ET = (int64_t)E * T;
   int loaded = -1;
@@ -142,7 +148,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
     if (has) loaded = oid;
     for (int l = tid; l < L; l += NEU_THREADS) pose_from_state(q.link_state, (int64_t)e * L + l, EL, lpose[l]);
     if (q.obj_state && tid == NEU_THREADS - 1) pose_from_state(q.obj_state, e, E, *opose);
-    for (int i = tid; i < 10 * L; i += NEU_THREADS) sums[i] = 0.f;
+    for (int i = tid; i < (NEU_THREADS / 64) * 10 * L; i += NEU_THREADS) sums[i] = 0.f;
     __syncthreads();
     const Pose* Op = q.obj_state ? opose : nullptr;
     GridDesc gd;
@@ -250,7 +256,8 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
 #pragma unroll
           for (int c = 0; c < 10; ++c) {
             const float t = wave_sum(sel ? v[c] : 0.f);
-            if (lane == 0) atomicAdd(&sums[c * L + lk], t);
+            // this wave's own slot: its LDS adds complete in issue order, so the sum is fixed
+            if (lane == 0) atomicAdd(&sums[(wave * 10 + c) * L + lk], t);
           }
           left &= ~__ballot(sel);
         }
@@ -260,7 +267,7 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
       __syncthreads();
       for (int i = tid; i < 10 * L; i += NEU_THREADS) {
         const int c = i / L, l = i - c * L;
-        const float a = sums[i];
+        const float a = ((sums[i] + sums[10 * L + i]) + sums[20 * L + i]) + sums[30 * L + i];
         const int64_t col = (int64_t)l * E + e;
         if (c < 6) {
           q.link_sums[c * EL + col] = a;

@@ -196,3 +196,26 @@ def test_c4_full_size_sampled(torch_cuda):
     r = oracle.run_readout(sc, sub, envs=envs, precision="f32", nsdf_params=P, nsdf_band=0.0)
     info = neural_tolerances(g, r, sc.force, sc.layout.pos, max_spin(sub))
     assert info["contacts"] > 0
+
+
+def test_neural_rollout_is_bitwise_repeatable(torch_cuda):
+    """Two rollouts of the same inputs give bit-identical outputs, link sums included (each wave
+    sums its links into its own LDS slot; the slots are added in wave order)."""
+    torch = torch_cuda
+    from paper_2606_22332_amd import binding as B
+    sc = clean_scene(E=40, S=2, cfg="c3")
+    inp = synth.make_inputs(sc)
+    P = torch.from_numpy(params_for(sc, seed=7)).cuda()
+    d = B.to_device(inp)
+    outs = []
+    for _ in range(2):
+        ro = B.Readout(sc, CLEAN_MASK, nsdf_params=P, nsdf_band=1e-3)
+        ro.alloc_outputs(2)
+        ro.rollout(d, 2)
+        torch.cuda.synchronize()
+        outs.append({k: v.cpu().numpy() for k, v in ro.out.items()})
+        ro.out = {}
+        ro.close()
+    for k in outs[0]:
+        assert np.array_equal(outs[0][k], outs[1][k], equal_nan=True), k
+    assert np.abs(outs[0]["link_sums"]).max() > 0
