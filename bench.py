@@ -201,14 +201,18 @@ def bench_c4(args) -> dict:
     inp = synth.make_inputs(sc)
     E, L, T, S = sc.num_envs, sc.layout.num_links, sc.layout.num_taxels, inp.link_state.shape[0]
     n_obj = len(sc.grids)
-    pts = synth.nsdf_points(sc.grids, args.nsdf_samples, seed=sc.geom_seed + 7)
+    if args.pair_lambda > 0:   # half the records as recipe points, each with a partner delta away
+        pts = synth.nsdf_pairs(synth.nsdf_points(sc.grids, args.nsdf_samples // 2, seed=sc.geom_seed + 7),
+                               args.pair_delta, seed=sc.geom_seed + 10)
+    else:
+        pts = synth.nsdf_points(sc.grids, args.nsdf_samples, seed=sc.geom_seed + 7)
     gen_s = time.perf_counter() - t0
     ns = B.Nsdf(sc.grids)
     rec = ns.targets(torch.from_numpy(pts).cuda())
     del pts
     P = torch.from_numpy(synth.nsdf_init(n_obj, sc.geom_seed + 8)).cuda()
     m, v = torch.zeros_like(P), torch.zeros_like(P)
-    hp = B.train_params(lr=1e-3, batch=1 << 14, seed=sc.geom_seed + 9)
+    hp = B.train_params(lr=1e-3, batch=1 << 14, seed=sc.geom_seed + 9, pair_lambda=args.pair_lambda)
     loss = torch.zeros((args.train_steps, n_obj), device="cuda")
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -223,7 +227,7 @@ def bench_c4(args) -> dict:
             if n_i <= 0:
                 continue
             lr_i = 1e-5 + 0.5 * (1e-3 - 1e-5) * (1.0 + np.cos(np.pi * (i + 0.5) / pieces))
-            hp_i = B.train_params(lr=float(lr_i), batch=1 << 14, seed=sc.geom_seed + 9)
+            hp_i = B.train_params(lr=float(lr_i), batch=1 << 14, seed=sc.geom_seed + 9, pair_lambda=args.pair_lambda)
             ns.train(P, m, v, rec, int(edges[i]), n_i, hp_i, loss=loss[int(edges[i]):int(edges[i + 1])])
     else:
         ns.train(P, m, v, rec, 0, args.train_steps, hp, loss=loss)
@@ -292,7 +296,8 @@ def bench_c4(args) -> dict:
                                                 "p90": float(np.quantile(ang[net], 0.9)) if net.any() else 0.0,
                                                 "p99": q99(ang[net])}},
         "training": {"steps": args.train_steps, "batch_per_object": 1 << 14, "samples_per_object": args.nsdf_samples,
-                     "lr_schedule": args.lr_schedule,
+                     "lr_schedule": args.lr_schedule, "pair_lambda": args.pair_lambda,
+                     "pair_delta_m": args.pair_delta if args.pair_lambda > 0 else None,
                      "ms_total": train_ms, "ms_per_step": train_ms / args.train_steps,
                      "final_l1_um_median": float(np.median(loss_um)), "final_l1_um_max": float(loss_um.max())},
         "memory_MB": {"grids_fp32": n_obj * sc.grids[0].n ** 3 * 4 / 1e6,
@@ -318,6 +323,9 @@ def main():
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--nsdf-samples", type=int, default=1 << 17)
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"])
+    ap.add_argument("--pair-lambda", type=float, default=0.0,
+                    help="weight of the pair term of the training loss (0: the plain L1 recipe)")
+    ap.add_argument("--pair-delta", type=float, default=5e-4, help="distance between the points of a pair [m]")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:

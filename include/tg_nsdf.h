@@ -45,6 +45,10 @@ typedef struct {
   float lr, beta1, beta2, eps; /* Adam; e.g. 1e-3, 0.9, 0.999, 1e-8 */
   int32_t batch;               /* samples per object per step, a multiple of 64 */
   uint64_t seed;               /* Philox4x32-10 key of the minibatch draw */
+  float pair_lambda;           /* 0: plain L1 loss.  > 0: records 2i and 2i+1 form a pair (n even)
+                                  and the loss adds pair_lambda * |r_2i+1 - r_2i| per pair, the
+                                  error of the difference across the pair (a first-order hold on
+                                  the slope between nearby points), divided by the batch */
 } tg_nsdf_train_params;
 
 /* Create / destroy.  create copies the grids to the device and allocates one packed BF16
@@ -59,11 +63,13 @@ const char* tg_nsdf_last_error(const tg_nsdf* h);
  * samples: device [num_objects][n][4]. */
 tg_status tg_nsdf_targets(tg_nsdf* h, const float* points, int64_t n, float* samples, void* hip_stream);
 
-/* Full-batch loss gradient: for every object o, grad[o] = d/dP mean_i |out(x_i) - t_i| over the
- * n records samples[o][0..n) and loss[o] = that mean.  params: device [num_objects][15681];
- * grad: device [num_objects][15681] (written); loss: device [num_objects] or NULL. */
-tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, int64_t n, float* grad,
-                       float* loss, void* hip_stream);
+/* Full-batch loss gradient: for every object o, grad[o] = d/dP of the loss over the n records
+ * samples[o][0..n) and loss[o] = that loss: mean_i |out(x_i) - t_i|, plus, for pair_lambda > 0
+ * (n even), pair_lambda * sum over pairs |r_2i+1 - r_2i| / n.  params: device
+ * [num_objects][15681]; grad: device [num_objects][15681] (written); loss: device [num_objects]
+ * or NULL.  TG_ERR_INVALID_ARGUMENT for pair_lambda < 0 or an odd n with pair_lambda > 0. */
+tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, int64_t n, float pair_lambda,
+                       float* grad, float* loss, void* hip_stream);
 
 /* One Adam step over count contiguous parameters at step number t (>= 1):
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;  p -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps). */
@@ -73,7 +79,9 @@ tg_status tg_nsdf_adam(float* params, float* m, float* v, const float* grad, int
 /* n_steps fused training steps (steps step0+1 .. step0+n_steps), all objects at once, one
  * workgroup per object.  Each step draws hp->batch record indices per object uniformly from
  * [0, n): Philox4x32-10 with key (seed low, seed high) and counter (object, step, j / 4, 8),
- * word j % 4, index = (word * n) >> 32; then forward, backward, Adam.  params, m, v: device
+ * word j % 4, index = (word * n) >> 32; with hp->pair_lambda > 0 it draws pairs instead: counter
+ * (object, step, j / 8, 8), word (j / 2) % 4, pair = (word * n/2) >> 32, index = 2 pair + j % 2
+ * (n even).  Then forward, backward, Adam.  params, m, v: device
  * [num_objects][15681], updated in place.  loss: device [n_steps][num_objects] (mean |r| of
  * each step's minibatch) or NULL. */
 tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const float* samples, int64_t n,

@@ -15,6 +15,7 @@
  */
 #define _GNU_SOURCE
 #include <math.h>
+#include <stdlib.h>
 #include <stdint.h>
 #include <string.h>
 
@@ -119,20 +120,38 @@ void or_nsdf_forward(const double* P, int64_t n, const double* x, double* out, d
  * bf16 = 1 emulates a BF16 MFMA backward: the forward as in or_nsdf_forward, and every GEMM
  * operand of the backward rounded to BF16 (dz in both the weight and the input gradient, the
  * layer inputs in the weight gradient, the weights in the input gradient); the output layer
- * and all sums stay wide. */
-double or_nsdf_loss_grad(const double* P, int64_t n, const double* x, const double* target, double* grad, int bf16) {
+ * and all sums stay wide.
+ * pair_lambda > 0 (n even): points 2i and 2i+1 form a pair, and the loss adds, per pair,
+ * pair_lambda * |(out_2i+1 - out_2i) - (t_2i+1 - t_2i)|, the error of the difference across the
+ * pair (a first-order handle on the slope), also divided by n. */
+double or_nsdf_loss_grad(const double* P, int64_t n, const double* x, const double* target, double* grad, int bf16,
+                         double pair_lambda) {
   const double *W[5], *b[5];
   param_views(P, W, b);
   double *GW[5], *Gb[5];
   param_views(grad, (const double**)GW, (const double**)Gb);
   memset(grad, 0, sizeof(double) * NS_NPARAM);
   double loss = 0;
+  double* res = NULL;   // residuals out - t of every point, for the pair term
+  if (pair_lambda > 0) {
+    res = (double*)malloc(sizeof(double) * (size_t)n);
+    for (int64_t s = 0; s < n; ++s) {
+      double z[4][NS_H], a[5][NS_H];
+      res[s] = forward1(P, x + 3 * s, z, a, bf16) - target[s];
+    }
+  }
   for (int64_t s = 0; s < n; ++s) {
     double z[4][NS_H], a[5][NS_H];
     const double out = forward1(P, x + 3 * s, z, a, bf16);
     const double r = out - target[s];
     loss += fabs(r);
-    const double go = (r > 0 ? 1.0 : (r < 0 ? -1.0 : 0.0)) / (double)n;
+    double go = (r > 0 ? 1.0 : (r < 0 ? -1.0 : 0.0)) / (double)n;
+    if (pair_lambda > 0) {
+      // d/d out_s of lambda |r_odd - r_even| is lambda * sign(r_s - r_partner) for both members
+      const double dr = r - res[s ^ 1];
+      go += pair_lambda * (dr > 0 ? 1.0 : (dr < 0 ? -1.0 : 0.0)) / (double)n;
+      if ((s & 1) == 0) loss += pair_lambda * fabs(dr);
+    }
     Gb[4][0] += go;
     double g[NS_H];
     for (int i = 0; i < NS_H; ++i) {
@@ -158,6 +177,7 @@ double or_nsdf_loss_grad(const double* P, int64_t n, const double* x, const doub
       }
     }
   }
+  free(res);
   return loss / (double)n;
 }
 

@@ -223,7 +223,8 @@ def _nsdf_lib():
     if not getattr(lib, "_nsdf_ready", False):
         lib.or_nsdf_num_params.restype = C.c_int
         lib.or_nsdf_forward.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
-        lib.or_nsdf_loss_grad.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        lib.or_nsdf_loss_grad.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int,
+                                          C.c_double]
         lib.or_nsdf_loss_grad.restype = C.c_double
         lib.or_nsdf_adam.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_double,
                                      C.c_double, C.c_double, C.c_double]
@@ -247,14 +248,18 @@ def nsdf_forward(P, x, grad=False, bf16=False):
     return (out, gx) if grad else out
 
 
-def nsdf_loss_grad(P, x, target, bf16=False):
+def nsdf_loss_grad(P, x, target, bf16=False, pair_lambda=0.0):
+    """Mean L1 loss and its parameter gradient; pair_lambda > 0 adds the pair term over points
+    (2i, 2i+1) (see or_nsdf_loss_grad)."""
     lib = _nsdf_lib()
     P = np.ascontiguousarray(P, np.float64)
     x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
     t = np.ascontiguousarray(target, np.float64)
+    if pair_lambda > 0 and x.shape[0] % 2:
+        raise ValueError("the pair term needs an even number of points")
     g = np.zeros_like(P)
     loss = lib.or_nsdf_loss_grad(P.ctypes.data, x.shape[0], x.ctypes.data, t.ctypes.data, g.ctypes.data,
-                                  int(bf16))
+                                  int(bf16), float(pair_lambda))
     return loss, g
 
 

@@ -371,7 +371,7 @@ class TgNsdfConfig(C.Structure):
 
 class TgNsdfTrainParams(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-                ("batch", C.c_int32), ("seed", C.c_uint64)]
+                ("batch", C.c_int32), ("seed", C.c_uint64), ("pair_lambda", C.c_float)]
 
 
 _nsdf_ready = False
@@ -387,7 +387,7 @@ def _nsdf_lib() -> C.CDLL:
             "tg_nsdf_destroy": ([P], C.c_int),
             "tg_nsdf_last_error": ([P], C.c_char_p),
             "tg_nsdf_targets": ([P, P, I64, P, P], C.c_int),
-            "tg_nsdf_grad": ([P, P, P, I64, P, P, P], C.c_int),
+            "tg_nsdf_grad": ([P, P, P, I64, C.c_float, P, P, P], C.c_int),
             "tg_nsdf_adam": ([P, P, P, P, I64, I64, P, P], C.c_int),
             "tg_nsdf_train": ([P, P, P, P, P, I64, I64, C.c_int32, P, P, P], C.c_int),
             "tg_nsdf_query": ([P, P, P, I64, P, P, P, P], C.c_int),
@@ -400,8 +400,9 @@ def _nsdf_lib() -> C.CDLL:
     return lib
 
 
-def train_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, batch=16384, seed=0) -> TgNsdfTrainParams:
-    return TgNsdfTrainParams(lr, beta1, beta2, eps, batch, seed)
+def train_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, batch=16384, seed=0,
+                 pair_lambda=0.0) -> TgNsdfTrainParams:
+    return TgNsdfTrainParams(lr, beta1, beta2, eps, batch, seed, pair_lambda)
 
 
 class Nsdf:
@@ -445,13 +446,13 @@ class Nsdf:
                   "tg_nsdf_targets")
         return samples
 
-    def grad(self, params, samples, stream=None):
+    def grad(self, params, samples, pair_lambda=0.0, stream=None):
         import torch
         n = samples.shape[1]
         g = torch.empty_like(params)
         loss = torch.empty(self.n_obj, dtype=torch.float32, device=params.device)
-        self._chk(self.lib.tg_nsdf_grad(self.h, params.data_ptr(), samples.data_ptr(), n, g.data_ptr(),
-                                        loss.data_ptr(), _stream_ptr(stream)), "tg_nsdf_grad")
+        self._chk(self.lib.tg_nsdf_grad(self.h, params.data_ptr(), samples.data_ptr(), n, float(pair_lambda),
+                                        g.data_ptr(), loss.data_ptr(), _stream_ptr(stream)), "tg_nsdf_grad")
         return loss, g
 
     def adam(self, params, m, v, grad, t, hp: TgNsdfTrainParams, stream=None):

@@ -133,18 +133,26 @@ __device__ __forceinline__ float bf_sum8(u32x4 v) {
 }
 
 // Forward and backward of this wave's tile; stages dz and layer inputs of every layer.
+// Samples 2i and 2i+1 of a tile (lanes s and s ^ 1) are a pair when pair_lambda > 0.
 __device__ __forceinline__ void tile_backprop(const Img& im, uint8_t* smem, int wave, int lane, float4 rec, bool valid,
-                                              float inv_n, float dw5[4][4], float& db5, float& loss,
-                                              const uint16_t* tab) {
+                                              float inv_n, float pair_lambda, float dw5[4][4], float& db5,
+                                              float& loss, const uint16_t* tab) {
   const int g = lane >> 4, s = lane & 15;
   uint32_t z[4][8];
   u32x4 pe[2];
   float a4[4][4];
   const float out = forward_tile(im, lane, rec.x, rec.y, rec.z, z, pe, a4, tab);
   const float r = out - rec.w;
-  const float go = valid ? ((r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) * inv_n) : 0.f;
+  float go = valid ? ((r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) * inv_n) : 0.f;
+  float lp = fabsf(r);
+  if (pair_lambda > 0.f) {   // uniform
+    // d/d out of lambda |r_odd - r_even| is lambda sign(r_self - r_partner) on both members
+    const float dr = r - __shfl_xor(r, 1);
+    if (valid) go += pair_lambda * ((dr > 0.f ? 1.f : (dr < 0.f ? -1.f : 0.f)) * inv_n);
+    if ((s & 1) == 0) lp += pair_lambda * fabsf(dr);
+  }
   if (g == 0 && valid) {
-    loss += fabsf(r);
+    loss += lp;
     db5 += go;
   }
   float gr[4][4];
@@ -226,6 +234,7 @@ struct FitArgs {
   int n_steps, n_obj, batch;
   float lr, b1, b2, eps;
   uint32_t key0, key1;
+  float pair_lambda;        // > 0: records (2i, 2i+1) are pairs, loss adds lambda |r_odd - r_even|
   const uint16_t* silu;     // SiLU table (global copy; staged in LDS)
 };
 
@@ -267,17 +276,20 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
       bool valid;
       int64_t idx;
       if (TRAIN) {
-        uint32_t x0 = (uint32_t)o, x1 = (uint32_t)step, x2 = (uint32_t)(j >> 2), x3 = 8u;
+        const bool pairs = a.pair_lambda > 0.f;   // uniform: draw pairs, lanes s and s ^ 1 share one
+        const int64_t jj = pairs ? (j >> 1) : j;
+        uint32_t x0 = (uint32_t)o, x1 = (uint32_t)step, x2 = (uint32_t)(jj >> 2), x3 = 8u;
         philox4x32_10(x0, x1, x2, x3, a.key0, a.key1);
-        const uint32_t wsel = (j & 3) == 0 ? x0 : ((j & 3) == 1 ? x1 : ((j & 3) == 2 ? x2 : x3));
-        idx = (int64_t)(((uint64_t)wsel * (uint64_t)a.n) >> 32);
+        const uint32_t wsel = (jj & 3) == 0 ? x0 : ((jj & 3) == 1 ? x1 : ((jj & 3) == 2 ? x2 : x3));
+        if (pairs) idx = 2 * (int64_t)(((uint64_t)wsel * (uint64_t)(a.n >> 1)) >> 32) + (j & 1);
+        else idx = (int64_t)(((uint64_t)wsel * (uint64_t)a.n) >> 32);
         valid = true;
       } else {
         idx = j;
         valid = j < a.n;
       }
       const float4 rec = valid ? So[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-      tile_backprop(im, smem, wave, lane, rec, valid, inv_n, dw5, db5, lossp, tab);
+      tile_backprop(im, smem, wave, lane, rec, valid, inv_n, a.pair_lambda, dw5, db5, lossp, tab);
       __syncthreads();
       owner_wgrad(smem, L, lane, acc, dbp);
       __syncthreads();
@@ -543,10 +555,12 @@ tg_status tg_nsdf_targets(tg_nsdf* h, const float* points, int64_t n, float* sam
   return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
 }
 
-tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, int64_t n, float* grad, float* loss,
-                       void* stream) {
+tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, int64_t n, float pair_lambda,
+                       float* grad, float* loss, void* stream) {
   if (!h) return TG_ERR_INVALID_ARGUMENT;
   if (!params || !samples || !grad || n < 1) return nfail(h, TG_ERR_INVALID_ARGUMENT, "grad: null pointer or n < 1");
+  if (!(pair_lambda >= 0.f) || (pair_lambda > 0.f && (n & 1)))
+    return nfail(h, TG_ERR_INVALID_ARGUMENT, "grad: pair_lambda must be >= 0, with an even n when > 0");
   if (!aligned16(samples)) return nfail(h, TG_ERR_INVALID_ARGUMENT, "grad: samples not 16-byte aligned");
   hipError_t e = hipFuncSetAttribute((const void*)nsdf_fit_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      LDS_FIT);
@@ -558,6 +572,7 @@ tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, in
   a.grad = grad;
   a.loss = loss;
   a.n_obj = h->n_obj;
+  a.pair_lambda = pair_lambda;
   a.silu = h->d_silu;
   hipLaunchKernelGGL(nsdf_fit_kernel<0>, dim3(h->n_obj), dim3(NT), LDS_FIT, (hipStream_t)stream, a);
   e = hipGetLastError();
@@ -581,6 +596,8 @@ tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const flo
   if (n < 1 || n > 0xffffffffLL || step0 < 0 || n_steps < 1 || step0 + n_steps > 0xffffffffLL)
     return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: bad n / step range");
   if (hp->batch < 64 || hp->batch % 64) return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: batch must be a multiple of 64");
+  if (!(hp->pair_lambda >= 0.f) || (hp->pair_lambda > 0.f && (n & 1)))
+    return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: pair_lambda must be >= 0, with an even n when > 0");
   if (!aligned16(samples)) return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: samples not 16-byte aligned");
   hipError_t e = hipFuncSetAttribute((const void*)nsdf_fit_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      LDS_FIT);
@@ -602,6 +619,7 @@ tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const flo
   a.eps = hp->eps;
   a.key0 = (uint32_t)hp->seed;
   a.key1 = (uint32_t)(hp->seed >> 32);
+  a.pair_lambda = hp->pair_lambda;
   a.silu = h->d_silu;
   hipLaunchKernelGGL(nsdf_fit_kernel<1>, dim3(h->n_obj), dim3(NT), LDS_FIT, (hipStream_t)stream, a);
   e = hipGetLastError();

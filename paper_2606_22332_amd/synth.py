@@ -543,3 +543,15 @@ def nsdf_points(grids: List[Grid], n: int, seed: int, sigma: float = 2e-3) -> np
         uni = rng.uniform(lo, hi, (n - ns, 3))
         out[o] = np.clip(np.concatenate([near, uni]), lo, hi)
     return out
+
+
+def nsdf_pairs(points: np.ndarray, delta: float, seed: int) -> np.ndarray:
+    """Pairs for the pair term of the training loss: float32 [n_obj, 2n, 3] with point i at 2i and
+    a partner at 2i+1, delta away in a uniformly random direction (object frame, not clamped;
+    the targets clamp into the box)."""
+    rng = np.random.default_rng(seed)
+    n_obj, n, _ = points.shape
+    out = np.empty((n_obj, 2 * n, 3), dtype=np.float32)
+    out[:, 0::2] = points
+    out[:, 1::2] = (points.astype(np.float64) + delta * random_unit(rng, n_obj * n).reshape(n_obj, n, 3)).astype(np.float32)
+    return out

@@ -128,7 +128,10 @@ def layer_rel(a, b):
     return {k: np.linalg.norm(a[s:e] - b[s:e]) / max(np.linalg.norm(b[s:e]), 1e-30) for k, (s, e) in LAYERS.items()}
 
 
-def test_grad_matches_oracle(torch_cuda, grids):
+@pytest.mark.parametrize("lam", [0.0, 0.5])
+def test_grad_matches_oracle(torch_cuda, grids, lam):
+    """Full-batch loss gradient against the oracle (FP64 and BF16-emulating), with and without
+    the pair term (records 2i and 2i+1 paired)."""
     torch = torch_cuda
     from paper_2606_22332_amd import binding as B
     gs = grids[:3]
@@ -136,19 +139,20 @@ def test_grad_matches_oracle(torch_cuda, grids):
     P = init_params(len(gs), 31)
     S = records(gs, n, 32)
     ns = B.Nsdf(gs)
-    loss, G = ns.grad(torch.from_numpy(P).cuda(), torch.from_numpy(S).cuda())
+    loss, G = ns.grad(torch.from_numpy(P).cuda(), torch.from_numpy(S).cuda(), pair_lambda=lam)
     torch.cuda.synchronize()
     loss, G = loss.cpu().numpy(), G.cpu().numpy()
     ns.close()
     for o in range(len(gs)):
         x, t = S[o, :, :3].astype(np.float64), S[o, :, 3].astype(np.float64)
-        l64, g64 = oracle.nsdf_loss_grad(P[o].astype(np.float64), x, t)
-        lbf, gbf = oracle.nsdf_loss_grad(P[o].astype(np.float64), x, t, bf16=True)
+        l64, g64 = oracle.nsdf_loss_grad(P[o].astype(np.float64), x, t, pair_lambda=lam)
+        lbf, gbf = oracle.nsdf_loss_grad(P[o].astype(np.float64), x, t, bf16=True, pair_lambda=lam)
         r64 = layer_rel(G[o].astype(np.float64), g64)
         rbf = layer_rel(G[o].astype(np.float64), gbf)
         print(dict(obj=o, loss_gpu=float(loss[o]), loss_bf=lbf, loss_64=l64, vs64=r64, vsbf=rbf))
-        # the loss is a mean of |out - t|: it moves by at most the forward tolerance (20 um / e)
-        assert abs(loss[o] - lbf) <= 20e-6 / half_extent(gs[o])
+        # the loss is a mean of |out - t| (plus lam |r_odd - r_even| per pair): it moves by at most
+        # the forward tolerance (20 um / e) per point, times (1 + 2 lam / 2) with the pair term
+        assert abs(loss[o] - lbf) <= (1 + lam) * 20e-6 / half_extent(gs[o])
         assert max(r64.values()) <= 1e-2, r64
         assert max(rbf.values()) <= 5e-3, rbf
 

@@ -4,6 +4,7 @@ fit that converges."""
 import math
 
 import numpy as np
+import pytest
 
 import oracle
 
@@ -40,20 +41,26 @@ def test_parameter_count():
     assert oracle.nsdf_num_params() == NP == 48 * 64 + 64 + 3 * (64 * 64 + 64) + 64 + 1
 
 
-def test_loss_gradient_matches_central_differences():
+@pytest.mark.parametrize("lam", [0.0, 0.7])
+def test_loss_gradient_matches_central_differences(lam):
+    """The loss gradient against central differences of the loss; with lam > 0 the loss is
+    also checked against its definition, mean |r| plus lam times the mean over the points of
+    |r_2i+1 - r_2i| counted once per pair, from the plain forward pass."""
     rng = np.random.default_rng(0)
     P = he_init(rng)
     P[offsets()[0][1]:offsets()[0][1] + H] = rng.normal(0, 0.1, H)     # nonzero biases too
     x = rng.uniform(-1, 1, (16, 3))
     t = rng.normal(0, 0.3, 16)
-    _, g = oracle.nsdf_loss_grad(P, x, t)
+    loss, g = oracle.nsdf_loss_grad(P, x, t, pair_lambda=lam)
+    r = oracle.nsdf_forward(P, x) - t
+    assert loss == pytest.approx((np.abs(r).sum() + lam * np.abs(r[1::2] - r[0::2]).sum()) / 16, rel=1e-12)
     idx = np.concatenate([rng.choice(NP, 200, replace=False), [NP - 1, NP - 2, 0]])
     h = 1e-6
     for i in idx:
         Pp, Pm = P.copy(), P.copy()
         Pp[i] += h
         Pm[i] -= h
-        fd = (oracle.nsdf_loss_grad(Pp, x, t)[0] - oracle.nsdf_loss_grad(Pm, x, t)[0]) / (2 * h)
+        fd = (oracle.nsdf_loss_grad(Pp, x, t, pair_lambda=lam)[0] - oracle.nsdf_loss_grad(Pm, x, t, pair_lambda=lam)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
 
 
