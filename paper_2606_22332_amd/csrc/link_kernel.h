@@ -84,10 +84,18 @@ __device__ __forceinline__ float group8_sum(float v) {
 __device__ __forceinline__ void put_group_sums(float* P, int ngroups, const float* v) {
   const bool lead = (threadIdx.x & 7) == 0;
   const int g = threadIdx.x >> 3;
+  // the three DPP stages run across all ten channels in turn, so no stage reads a value written
+  // by the instruction just before it (no hazard wait states between dependent DPP adds)
+  float t[10];
 #pragma unroll
-  for (int c = 0; c < 10; ++c) {
-    const float t = group8_sum(v[c]);
-    if (lead) P[c * ngroups + g] = t;
+  for (int c = 0; c < 10; ++c) t[c] = v[c] + dpp_f<0xB1>(v[c]);
+#pragma unroll
+  for (int c = 0; c < 10; ++c) t[c] = t[c] + dpp_f<0x4E>(t[c]);
+#pragma unroll
+  for (int c = 0; c < 10; ++c) t[c] = t[c] + dpp_f<0x104>(t[c]);
+  if (lead) {
+#pragma unroll
+    for (int c = 0; c < 10; ++c) P[c * ngroups + g] = t[c];
   }
 }
 
