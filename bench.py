@@ -329,7 +329,7 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
               "(environments shard across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 

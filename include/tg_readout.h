@@ -45,7 +45,7 @@ typedef enum {
   TG_ERR_INVALID_ARGUMENT = 1, /* null/misaligned pointer, bad size or parameter */
   TG_ERR_OUT_OF_MEMORY = 2,    /* device allocation failed in create */
   TG_ERR_HIP = 3,              /* a HIP runtime call failed */
-  TG_ERR_UNSUPPORTED = 4,      /* a configuration this build does not implement */
+  TG_ERR_UNSUPPORTED = 4,      /* a configuration this library does not implement */
   TG_ERR_UNSTABLE = 5,         /* thermal configuration violates the explicit stability limit */
   TG_ERR_STATE = 6             /* call not valid in the handle's current state */
 } tg_status;
