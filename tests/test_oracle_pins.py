@@ -602,3 +602,148 @@ def test_fp32_oracle_tracks_fp64_reference():
     rel = np.abs(fa - fb).max(-1) / np.abs(fb).max(-1)
     assert np.quantile(rel, 0.99) < 1e-4
     np.testing.assert_allclose(a["prox"], b["prox"], atol=2e-6)
+
+
+# ---------------------------------------------------------------------------------------------- point velocities
+# App. A.5 (KinematicTaxel): the relative velocity at the probe centre is
+#   v_rel = R_L^T ( v_C(q) - v_L(q) ),  v_C(q) = v_O + w_O x (q - p_O),  v_L(q) = v_L + w_L x (q - p_L),
+# and F_n = max(0, k_n s + c_n s v_n), f_t = -k_t v_t capped at mu F_n.  The pins below put an
+# off-centre taxel on the plane z = 0 with the link (or the object) spinning about the contact
+# normal, and a probe approaching or leaving the plane at a known normal speed; every expected
+# value is worked out by hand from those equations in the test's docstring.
+_SPIN_TAXEL = (0.002, 0.001, 0.0)     # link frame, off the link origin
+_LINK_XY = (0.01, -0.02)              # the link origin is off the world origin too
+
+
+def _spin_scene(height, link_w=(0, 0, 0), obj=None, force=None):
+    lay = H.layout_from([_SPIN_TAXEL])
+    sc = H.scene(lay, [H.plane_grid()], force=force)
+    poses = H.pose(p=(_LINK_XY[0], _LINK_XY[1], height), q=DOWN, w=link_w)[None, None]
+    o = oracle.Oracle(sc, None, "f64")
+    return o.run(H.inputs(poses, obj_state=None if obj is None else np.asarray(obj, np.float64)[None]))
+
+
+@pytest.mark.parametrize("wz", [50.0, -80.0, 500.0])
+def test_link_spin_about_the_normal_gives_the_point_velocity_friction(wz):
+    """Link spinning at w about world z (the plane normal), taxel x_j = (a, b, 0), link turned by DOWN
+    (R_L = diag(1, -1, -1)).  Then q - p_L = R_L x_j = (a, -b, 0) and v_L(q) = w z x (a, -b, 0) = (w b, w a, 0)
+    in the world; v_rel = R_L^T (0 - v_L(q)) = (-w b, w a, 0), normal to the plane v_n = 0, so
+    f_t = -k_t v_rel = k_t w (b, -a, 0), capped at mu k_n d.  The torsion term sees (w_O - w_L) . m = -w,
+    so tau = x_j x f - k_w (-w) m_bar = x_j x f - (0, 0, k_w w)."""
+    fp = synth.ForceParams()
+    h = 0.4e-3
+    out = _spin_scene(h, link_w=(0, 0, wz), force=fp)
+    a, b = (float(np.float32(c)) for c in _SPIN_TAXEL[:2])
+    w = float(np.float32(wz))
+    d = out["depth"][0, 0, 0]
+    assert abs(d - (float(np.float32(1e-3)) - float(np.float32(h)))) < 1e-8   # FP32 node values of the plane
+    Fn = fp.k_n * d
+    ft = fp.k_t * w * np.array([b, -a, 0.0])
+    lim = float(np.float32(fp.mu)) * Fn
+    nft = np.linalg.norm(ft)
+    if nft > lim:
+        ft = ft * (lim / nft)
+    f = ft + Fn * np.array([0.0, 0.0, -1.0])
+    np.testing.assert_allclose(out["ft"][0, :3, 0, 0], f, rtol=1e-12, atol=1e-15)
+    x = np.array([a, b, 0.0])
+    tau = np.cross(x, f) - np.array([0.0, 0.0, fp.k_w * w])
+    np.testing.assert_allclose(out["ft"][0, 3:, 0, 0], tau, rtol=1e-12, atol=1e-15)
+    # the case split is exercised: 50 and -80 rad/s stay inside the cone, 500 rad/s is capped
+    assert (nft > lim) == (abs(wz) > 200)
+
+
+@pytest.mark.parametrize("wz", [20.0, 400.0])
+def test_object_spin_about_the_normal_gives_the_point_velocity_friction(wz):
+    """Static link over a plane object whose frame sits at p_O = (p, q, 0) with identity orientation and
+    spins at w_O = (0, 0, w).  The probe centre is q_j = p_L + R_L x_j = (L_x + a, L_y - b, h), so
+    v_C(q) = w z x (q_j - p_O) = w (-(L_y - b - p_y), L_x + a - p_x, 0) and v_rel = R_L^T v_C(q)
+    flips the y component; v_n = 0 and f_t = -k_t v_rel (capped).  Torsion: (w_O - w_L) . m = w,
+    so tau = x_j x f - k_w w m_bar = x_j x f + (0, 0, k_w w)."""
+    fp = synth.ForceParams()
+    h = 0.4e-3
+    pO = (0.004, -0.015, 0.0)
+    obj = H.pose(p=pO, w=(0, 0, wz))
+    out = _spin_scene(h, obj=obj, force=fp)
+    a, b = (float(np.float32(c)) for c in _SPIN_TAXEL[:2])
+    Lx, Ly = (float(np.float32(c)) for c in _LINK_XY)
+    px, py = (float(np.float32(c)) for c in pO[:2])
+    w = float(np.float32(wz))
+    d = out["depth"][0, 0, 0]
+    Fn = fp.k_n * d
+    vC = w * np.array([-(Ly - b - py), Lx + a - px, 0.0])
+    vrel = vC * np.array([1.0, -1.0, -1.0])
+    ft = -fp.k_t * vrel
+    lim = float(np.float32(fp.mu)) * Fn
+    nft = np.linalg.norm(ft)
+    if nft > lim:
+        ft = ft * (lim / nft)
+    f = ft + Fn * np.array([0.0, 0.0, -1.0])
+    np.testing.assert_allclose(out["ft"][0, :3, 0, 0], f, rtol=1e-12, atol=1e-15)
+    tau = np.cross(np.array([a, b, 0.0]), f) + np.array([0.0, 0.0, fp.k_w * w])
+    np.testing.assert_allclose(out["ft"][0, 3:, 0, 0], tau, rtol=1e-12, atol=1e-15)
+    assert (nft > lim) == (wz > 200)
+
+
+@pytest.mark.parametrize("vz", [-0.1, 0.1, -2.0])
+def test_normal_damping_scales_with_depth(vz):
+    """A probe moving along the plane normal at world velocity (0, 0, v): v_rel = R_L^T (0, 0, -v) =
+    (0, 0, v) and m_bar = (0, 0, -1), so v_n = -v (approach, v < 0, gives v_n > 0) and
+    F_n = max(0, k_n d + c_n d v_n), the depth-weighted damping of App. A.5.  With d = 0.6 mm and
+    |v| = 0.1 m/s the damping adds c_n d |v| = 3e-4 N to 1.2 N, while a Kelvin-Voigt c_n v_n would add
+    0.5 N."""
+    fp = synth.ForceParams()
+    h = 0.4e-3
+    lay = H.layout_from([_SPIN_TAXEL])
+    sc = H.scene(lay, [H.plane_grid()], force=fp)
+    poses = H.pose(p=(_LINK_XY[0], _LINK_XY[1], h), q=DOWN, v=(0, 0, vz))[None, None]
+    out = oracle.Oracle(sc, None, "f64").run(H.inputs(poses))
+    d = out["depth"][0, 0, 0]
+    vn = -float(np.float32(vz))
+    Fn = max(0.0, fp.k_n * d + fp.c_n * d * vn)
+    f = np.array([0.0, 0.0, -Fn])
+    np.testing.assert_allclose(out["ft"][0, :3, 0, 0], f, rtol=1e-12, atol=1e-15)
+    a, b = (float(np.float32(c)) for c in _SPIN_TAXEL[:2])
+    np.testing.assert_allclose(out["ft"][0, 3:, 0, 0], np.cross([a, b, 0.0], f), rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------------------------- object frame
+def test_rotated_and_translated_object_frame():
+    """q_o = R_O^T (q - p_O) (App. A.1): a tilted plane phi_o(x) = n_o . x - c in the object frame, with the
+    object turned by a generic rotation and moved, reads the world-frame distance (R_O n_o) . (q - p_O) - c;
+    the contact normal is m = R_O n_o and m_bar = R_L^T m.  A transposed R_O (or R_O in place of R_O^T)
+    tilts the plane the other way and fails both checks."""
+    rng = np.random.default_rng(17)
+    no = np.array([0.3, -0.2, 0.93]); no /= np.linalg.norm(no)
+    c = 0.002
+    g = H.plane_grid(no, offset=c)
+    qO = H.quat_axis_angle([1.0, 2.0, 3.0], 0.7)
+    pO = np.array([0.006, -0.004, 0.003])
+    E = 300
+    lay = H.layout_from(synth.patch(4))
+    sc = H.scene(lay, [g], num_envs=E)
+    ql = rng.normal(size=(E, 4)); ql /= np.linalg.norm(ql, axis=1, keepdims=True)
+    pl = rng.uniform(-0.02, 0.02, size=(E, 3))
+    links = np.concatenate([pl, ql, np.zeros((E, 6))], axis=1)
+    objs = np.tile(np.concatenate([pO, qO, np.zeros(6)]), (E, 1))
+    inp = H.inputs(links[None], np.zeros(E), objs[None])
+    out = oracle.Oracle(sc, None, "f64").run(inp)
+    # expected values from the FP32-rounded inputs, in FP64
+    p32 = inp.link_state[0, 0:3].T.astype(np.float64)
+    q32 = inp.link_state[0, 3:7].T.astype(np.float64)
+    pO32 = inp.obj_state[0, 0:3, 0].astype(np.float64)
+    RO = H.rot_of_quat(inp.obj_state[0, 3:7, 0].astype(np.float64))
+    x = lay.pos.astype(np.float64)
+    nw = RO @ no
+    nhit = 0
+    for e in range(E):
+        RL = H.rot_of_quat(q32[e])
+        q = p32[e] + x @ RL.T
+        phi = (q - pO32) @ nw - c
+        np.testing.assert_allclose(out["surfdist"][0, e], phi, rtol=0, atol=2e-8)
+        dep = np.maximum(0.0, float(np.float32(1e-3)) - phi)
+        hit = dep > 1e-6
+        np.testing.assert_allclose(out["depth"][0, e, hit], dep[hit], rtol=0, atol=2e-8)
+        for j in np.nonzero(hit)[0]:
+            np.testing.assert_allclose(out["normal"][0, :, e, j], RL.T @ nw, rtol=0, atol=1e-6)
+            nhit += 1
+    assert nhit > 200

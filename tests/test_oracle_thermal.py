@@ -50,6 +50,24 @@ def test_constants_of_the_configuration():
     assert K["k_eff"] == pytest.approx(2 * 0.2 * 10 / 10.2, rel=1e-6)
 
 
+def test_source_rates_of_the_configuration_worked_by_hand():
+    """The per-step source coefficients of the configuration (dt = dx = 1 mm units, rho c_p = 2e6 J/m^3K),
+    worked out by hand from the thermal model's definitions and written here as numbers:
+      radiation  h_r = 4 * 0.85 * 5.6704e-8 W/m^2K^4 * (295.15 K)^3 = 4.9570 W/m^2K,
+                 rho_f = dt h_r / (rho c_p dx) = 1e-3 * 4.9570 / (2e6 * 1e-3) = 2.4785e-6 per face,
+      contact    k_eff = 2 * 0.2 * 10 / 10.2 = 0.39216 W/mK,
+                 kappa = dt pi d_w k_eff / (rho c_p dx^3) = 1e-3 * 3.14159 * 0.39216 / 2e-3 = 0.61600 per m of depth,
+      generation g = dt P_gen / (16^3 rho c_p dx^3) = 1e-4 / 8.192 = 1.2207e-5 K per step.
+    A dropped dx (area instead of volume), a missing pi or the wrong temperature scale moves them by far
+    more than the 1e-4 these figures are held to."""
+    K = oracle.thermal_constants(params())
+    assert K["h_r"] == pytest.approx(4.9570, rel=1e-4)
+    assert K["rho_f"] == pytest.approx(2.4785e-6, rel=1e-4)
+    assert K["k_eff"] == pytest.approx(0.39216, rel=1e-4)
+    assert K["kappa"] == pytest.approx(0.61600, rel=1e-4)
+    assert K["g"] == pytest.approx(1.2207e-5, rel=1e-4)
+
+
 @pytest.mark.parametrize("axis", [0, 1, 2])
 def test_cosine_mode_decays_at_the_discrete_eigenvalue(axis):
     n, steps = 16, 300
