@@ -230,6 +230,12 @@ def _nsdf_lib():
                                      C.c_double, C.c_double, C.c_double]
         lib.or_nsdf_targets.argtypes = [C.c_int32, C.c_void_p, C.c_float, C.c_void_p, C.c_int64, C.c_void_p,
                                         C.c_void_p]
+        lib.or_nsdf_targets2.argtypes = [C.c_int32, C.c_void_p, C.c_float, C.c_void_p, C.c_int64, C.c_void_p,
+                                         C.c_void_p, C.c_void_p]
+        lib.or_nsdf_loss_grad2.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                           C.c_int, C.c_double, C.c_double]
+        lib.or_nsdf_loss_grad2.restype = C.c_double
+        lib.or_nsdf_dirderiv.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         lib._nsdf_ready = True
     return lib
 
@@ -248,19 +254,36 @@ def nsdf_forward(P, x, grad=False, bf16=False):
     return (out, gx) if grad else out
 
 
-def nsdf_loss_grad(P, x, target, bf16=False, pair_lambda=0.0):
-    """Mean L1 loss and its parameter gradient; pair_lambda > 0 adds the pair term over points
-    (2i, 2i+1) (see or_nsdf_loss_grad)."""
+def nsdf_loss_grad(P, x, target, bf16=False, pair_lambda=0.0, gtarget=None, grad_lambda=0.0):
+    """Loss and its parameter gradient: mean L1 on the value; pair_lambda > 0 adds the pair term
+    over points (2i, 2i+1); grad_lambda > 0 with gtarget [n][3] adds the L1 term on the input
+    gradient (see or_nsdf_loss_grad2)."""
     lib = _nsdf_lib()
     P = np.ascontiguousarray(P, np.float64)
     x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
     t = np.ascontiguousarray(target, np.float64)
     if pair_lambda > 0 and x.shape[0] % 2:
         raise ValueError("the pair term needs an even number of points")
+    gt = None
+    if grad_lambda > 0:
+        gt = np.ascontiguousarray(gtarget, np.float64).reshape(-1, 3)
+        assert gt.shape == x.shape
     g = np.zeros_like(P)
-    loss = lib.or_nsdf_loss_grad(P.ctypes.data, x.shape[0], x.ctypes.data, t.ctypes.data, g.ctypes.data,
-                                  int(bf16), float(pair_lambda))
+    loss = lib.or_nsdf_loss_grad2(P.ctypes.data, x.shape[0], x.ctypes.data, t.ctypes.data, _ptr(gt), g.ctypes.data,
+                                   int(bf16), float(pair_lambda), float(grad_lambda))
     return loss, g
+
+
+def nsdf_dirderiv(P, x, u, bf16=False):
+    """Directional derivative of the network output along u[n][3] at x[n][3] by the forward-mode
+    tangent pass."""
+    lib = _nsdf_lib()
+    P = np.ascontiguousarray(P, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    u = np.ascontiguousarray(u, np.float64).reshape(-1, 3)
+    dd = np.zeros(x.shape[0])
+    lib.or_nsdf_dirderiv(P.ctypes.data, x.shape[0], x.ctypes.data, u.ctypes.data, dd.ctypes.data, int(bf16))
+    return dd
 
 
 def nsdf_adam(P, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
@@ -271,16 +294,18 @@ def nsdf_adam(P, m, v, g, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     lib.or_nsdf_adam(P.ctypes.data, m.ctypes.data, v.ctypes.data, g.ctypes.data, P.size, int(t), lr, b1, b2, eps)
 
 
-def nsdf_targets(grid, points):
-    """FP64 training records {x_hat, phi/e} of object-frame points for one grid (synth.Grid)."""
+def nsdf_targets(grid, points, grad=False):
+    """FP64 training records {x_hat, phi/e} of object-frame points for one grid (synth.Grid); with
+    grad=True also the grid's d phi / d q [n][3] at the clamped points."""
     lib = _nsdf_lib()
     pts = np.ascontiguousarray(points, np.float32).reshape(-1, 3)
     vals = np.ascontiguousarray(grid.values, np.float32)
     org = np.ascontiguousarray(grid.origin, np.float32)
     rec = np.zeros((pts.shape[0], 4))
-    lib.or_nsdf_targets(int(grid.n), org.ctypes.data, float(grid.spacing), vals.ctypes.data,
-                        pts.shape[0], pts.ctypes.data, rec.ctypes.data)
-    return rec
+    gr = np.zeros((pts.shape[0], 3)) if grad else None
+    lib.or_nsdf_targets2(int(grid.n), org.ctypes.data, float(grid.spacing), vals.ctypes.data,
+                         pts.shape[0], pts.ctypes.data, rec.ctypes.data, _ptr(gr))
+    return (rec, gr) if grad else rec
 
 
 # ------------------------------------------------------------------------------------------------

@@ -64,6 +64,94 @@ def test_loss_gradient_matches_central_differences(lam):
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
 
 
+@pytest.mark.parametrize("lam", [0.0, 0.7])
+def test_gradient_term_matches_its_definition_and_central_differences(lam):
+    """With the L1 term on the input gradient (grad_lambda > 0): the loss equals its definition,
+    mean |r| (plus the pair term) plus grad_lambda times the mean over the points of
+    sum_d |g_d - gt_d| with g from the plain reverse pass; its parameter gradient (through the
+    tangent pass and the second derivative of SiLU) matches central differences of that loss."""
+    rng = np.random.default_rng(5)
+    P = he_init(rng)
+    for w, b in offsets()[:4]:
+        P[b:b + H] = rng.normal(0, 0.1, H)
+    P[NP - 1] = 0.05
+    n = 16
+    x = rng.uniform(-1, 1, (n, 3))
+    t = rng.normal(0, 0.3, n)
+    gt = rng.normal(0, 1.0, (n, 3))
+    gl = 0.3
+    loss, g = oracle.nsdf_loss_grad(P, x, t, pair_lambda=lam, gtarget=gt, grad_lambda=gl)
+    out, gx = oracle.nsdf_forward(P, x, grad=True)
+    r = out - t
+    expect = (np.abs(r).sum() + lam * np.abs(r[1::2] - r[0::2]).sum() + gl * np.abs(gx - gt).sum()) / n
+    assert loss == pytest.approx(expect, rel=1e-12)
+    # the gradient term changes the parameter gradient in every layer
+    _, g0 = oracle.nsdf_loss_grad(P, x, t, pair_lambda=lam)
+    for w, b in offsets():
+        assert np.linalg.norm(g[w:b] - g0[w:b]) > 1e-3 * np.linalg.norm(g0[w:b])
+    lossf = lambda Q: oracle.nsdf_loss_grad(Q, x, t, pair_lambda=lam, gtarget=gt, grad_lambda=gl)[0]
+    idx = np.concatenate([rng.choice(NP, 200, replace=False), [NP - 1, NP - 2, 0]] +
+                         [np.arange(b, b + 3) for _, b in offsets()[:4]])
+    h = 1e-6
+    for i in idx:
+        Pp, Pm = P.copy(), P.copy()
+        Pp[i] += h
+        Pm[i] -= h
+        fd = (lossf(Pp) - lossf(Pm)) / (2 * h)
+        assert abs(fd - g[i]) <= 2e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_tangent_pass_is_the_directional_derivative():
+    """The forward-mode tangent pass along u gives u . (d out / d x_hat) of the reverse pass, and
+    the fourth-order central difference of the output along u."""
+    rng = np.random.default_rng(6)
+    P = he_init(rng)
+    x = rng.uniform(-1, 1, (30, 3))
+    u = rng.normal(0, 1, (30, 3))
+    dd = oracle.nsdf_dirderiv(P, x, u)
+    _, gx = oracle.nsdf_forward(P, x, grad=True)
+    np.testing.assert_allclose(dd, (gx * u).sum(1), rtol=1e-11, atol=1e-12)
+    h = 1e-5
+    f = lambda y: oracle.nsdf_forward(P, y)
+    fd = (-f(x + 2 * h * u) + 8 * f(x + h * u) - 8 * f(x - h * u) + f(x - 2 * h * u)) / (12 * h)
+    np.testing.assert_allclose(dd, fd, rtol=1e-6, atol=1e-7)
+    # BF16 emulation of the same pass stays within BF16 noise of the exact one
+    dbf = oracle.nsdf_dirderiv(P, x, u, bf16=True)
+    assert np.quantile(np.abs(dbf - dd) / np.maximum(np.abs(dd), 1e-3), 0.9) < 0.1
+
+
+def test_grid_gradient_targets():
+    """The grid gradient of the training targets: a linear field's gradient is its normal wherever
+    the point lies (trilinear interpolation reproduces it), and for a generic field the analytic
+    gradient equals the central difference of the interpolated value inside a cell."""
+    from helpers import grid_from, plane_grid
+    nrm = np.array([0.3, -0.5, 0.81])
+    nrm /= np.linalg.norm(nrm)
+    g = plane_grid(nrm, 0.004, n=16, side=0.06)
+    rng = np.random.default_rng(7)
+    pts = rng.uniform(-0.029, 0.029, (300, 3)).astype(np.float32)
+    rec, gr = oracle.nsdf_targets(g, pts, grad=True)
+    np.testing.assert_allclose(gr, np.broadcast_to(nrm, gr.shape), atol=2e-6)
+    g2 = grid_from(lambda P: np.sin(40 * P[..., 0]) * np.cos(30 * P[..., 1]) + 20 * P[..., 2] ** 2, n=16, side=0.06)
+    h = float(g2.spacing)
+    o = g2.origin.astype(np.float64)
+    # cell-centre neighbourhoods: the stencil stays inside one cell
+    cells = rng.integers(0, 15, (200, 3))
+    base = o + (cells + rng.uniform(0.3, 0.7, (200, 3))) * h
+    pts = base.astype(np.float32)
+    p64 = pts.astype(np.float64)
+    _, gr = oracle.nsdf_targets(g2, pts, grad=True)
+    e = 0.5 * (g2.n - 1) * h
+    for d in range(3):
+        step = np.zeros(3)
+        step[d] = 0.05 * h
+        hi = oracle.nsdf_targets(g2, (p64 + step).astype(np.float32))
+        lo = oracle.nsdf_targets(g2, (p64 - step).astype(np.float32))
+        dx = (hi[:, d] - lo[:, d]) * e          # the clamped points actually used, x_hat -> q
+        fd = (hi[:, 3] - lo[:, 3]) * e / dx
+        np.testing.assert_allclose(gr[:, d], fd, rtol=1e-6, atol=1e-6)
+
+
 def test_input_gradient_matches_central_differences():
     rng = np.random.default_rng(1)
     P = he_init(rng)
