@@ -97,6 +97,27 @@ tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const flo
 tg_status tg_nsdf_query(tg_nsdf* h, const float* params, const int64_t* offsets, int64_t max_count,
                         const float* xhat, float* out, float* grad, void* hip_stream);
 
+/* Allocation-free evaluation, for callers that cannot allocate device memory while they run:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and kernels as tg_nsdf_query, bit for bit; the difference is where the
+ * packed BF16 images live.  tg_nsdf_query packs them into the handle's own buffer; this call
+ * packs them into one static device array per GPU (TG_NSDF_QUERY_NOALLOC_SCRATCH_BYTES, about
+ * 4 MB, reserved on each GPU that runs it until the process ends) and calls no hipMalloc,
+ * hipFree or other allocating routine.  Its device address is looked up once per device, at
+ * the first call on that device.
+ *   - The handle's num_objects must be <= TG_NSDF_QUERY_NOALLOC_MAX_OBJECTS, else
+ *     TG_ERR_INVALID_ARGUMENT (nothing launched; use tg_nsdf_query).
+ *   - The current device must be the one the handle was created on, else
+ *     TG_ERR_INVALID_ARGUMENT.
+ *   - Every call on a GPU shares that GPU's array, which keeps the last call's images.  Each
+ *     call rewrites the images of all its objects before reading them, so nothing needs
+ *     clearing, but calls that overlap in time on one GPU (two streams, two threads) race on
+ *     the array: order them, for instance on one stream. */
+#define TG_NSDF_QUERY_NOALLOC_MAX_OBJECTS 64
+#define TG_NSDF_QUERY_NOALLOC_SCRATCH_BYTES (64 * 65024) /* max objects x bytes per image */
+tg_status tg_nsdf_query_noalloc(tg_nsdf* h, const float* params, const int64_t* offsets, int64_t max_count,
+                                const float* xhat, float* out, float* grad, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -391,6 +391,7 @@ def _nsdf_lib() -> C.CDLL:
             "tg_nsdf_adam": ([P, P, P, P, I64, I64, P, P], C.c_int),
             "tg_nsdf_train": ([P, P, P, P, P, I64, I64, C.c_int32, P, P, P], C.c_int),
             "tg_nsdf_query": ([P, P, P, I64, P, P, P, P], C.c_int),
+            "tg_nsdf_query_noalloc": ([P, P, P, I64, P, P, P, P], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -466,18 +467,24 @@ class Nsdf:
                                          n, int(step0), int(n_steps), C.byref(hp), lp, _stream_ptr(stream)),
                   "tg_nsdf_train")
 
-    def query(self, params, offsets, xhat, grad=True, stream=None):
-        """offsets: int64 list/array [n_obj+1] (points grouped by object); xhat: float32 [n, 3] on device."""
+    def query(self, params, offsets, xhat, grad=True, stream=None, noalloc=False, out=None, grad_out=None):
+        """offsets: int64 list/array [n_obj+1] (points grouped by object); xhat: float32 [n, 3] on device.
+        noalloc: call tg_nsdf_query_noalloc (images in the library's static device array) instead of
+        tg_nsdf_query.  out / grad_out: caller-provided result tensors ([n], [n, 3])."""
         import torch
         offs = np.asarray(offsets, np.int64)
         d_off = torch.from_numpy(offs).to(xhat.device)
         n = xhat.shape[0]
-        out = torch.empty(n, dtype=torch.float32, device=xhat.device)
-        g = torch.empty((n, 3), dtype=torch.float32, device=xhat.device) if grad else None
+        if out is None:
+            out = torch.empty(n, dtype=torch.float32, device=xhat.device)
+        g = grad_out
+        if grad and g is None:
+            g = torch.empty((n, 3), dtype=torch.float32, device=xhat.device)
         self._keep = d_off
-        self._chk(self.lib.tg_nsdf_query(self.h, params.data_ptr(), d_off.data_ptr(), int(np.diff(offs).max()),
-                                         xhat.data_ptr(), out.data_ptr(), g.data_ptr() if grad else None,
-                                         _stream_ptr(stream)), "tg_nsdf_query")
+        fn = self.lib.tg_nsdf_query_noalloc if noalloc else self.lib.tg_nsdf_query
+        name = "tg_nsdf_query_noalloc" if noalloc else "tg_nsdf_query"
+        self._chk(fn(self.h, params.data_ptr(), d_off.data_ptr(), int(np.diff(offs).max()) if offs.size > 1 else 0,
+                     xhat.data_ptr(), out.data_ptr(), g.data_ptr() if grad else None, _stream_ptr(stream)), name)
         return (out, g) if grad else out
 
     def close(self):

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -453,6 +454,7 @@ __global__ __launch_bounds__(NT) void nsdf_query_kernel(const uint32_t* __restri
 // ------------------------------------------------------------------------------------------------
 struct tg_nsdf {
   int n_obj = 0;
+  int device = -1;              // current device at create: every buffer below lives there
   BoxDesc* d_boxes = nullptr;
   float* d_vals = nullptr;
   uint32_t* d_img = nullptr;
@@ -473,6 +475,50 @@ hipError_t nsdf_pack_images(const float* params, int n_obj, uint32_t* images, hi
                      images);
   return hipGetLastError();
 }
+
+// Pack the parameters into per-object images at img, then evaluate the points (both launches on
+// the caller's stream).  Shared by the handle's own image buffer and the static one below.
+static tg_status launch_query(tg_nsdf* h, uint32_t* img, const float* params, const int64_t* offsets,
+                              int64_t max_count, const float* xhat, float* out, float* grad, hipStream_t s) {
+  hipLaunchKernelGGL(nsdf_pack_kernel, dim3((IMG_WORDS + 255) / 256, h->n_obj), dim3(256), 0, s, params, h->n_obj,
+                     img);
+  if (max_count > 0) {
+    const int64_t per_block = 4 * 16 * QUERY_TILES_PER_WAVE;
+    const dim3 grid((unsigned)((max_count + per_block - 1) / per_block), (unsigned)h->n_obj);
+    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES, s, img, offsets, xhat, out, grad, h->d_silu);
+  }
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+}
+
+// Images for the allocation-free evaluation: one static device array per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the host that name is
+// only a stand-in for the symbol); it uses the device address that hipGetSymbolAddress returns,
+// looked up once per device and kept in g_scratch_addr.
+static __device__ __align__(256) uint32_t scratch[(size_t)TG_NSDF_QUERY_NOALLOC_MAX_OBJECTS * IMG_WORDS];
+static_assert((size_t)TG_NSDF_QUERY_NOALLOC_MAX_OBJECTS * IMG_BYTES == TG_NSDF_QUERY_NOALLOC_SCRATCH_BYTES,
+              "header states the static scratch size");
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+uint32_t* g_scratch_addr[MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch array (the current device), looked up on first use.
+tg_status scratch_addr(tg_nsdf* h, int dev, uint32_t** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return nfail(h, TG_ERR_UNSUPPORTED, "query_noalloc: device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return nfail(h, TG_ERR_HIP, std::string("query_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+    g_scratch_addr[dev] = (uint32_t*)p;
+  }
+  *out = g_scratch_addr[dev];
+  return TG_OK;
+}
+}  // namespace
 
 extern "C" {
 
@@ -508,6 +554,10 @@ tg_status tg_nsdf_create(const tg_nsdf_config* cfg, tg_nsdf** out) {
   tg_nsdf* h = new (std::nothrow) tg_nsdf();
   if (!h) return nfail(nullptr, TG_ERR_OUT_OF_MEMORY, "host allocation failed");
   h->n_obj = cfg->num_objects;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return nfail(nullptr, TG_ERR_HIP, "hipGetDevice failed");
+  }
   if (hipMalloc(&h->d_boxes, sizeof(BoxDesc) * boxes.size()) != hipSuccess ||
       hipMalloc(&h->d_vals, sizeof(float) * total) != hipSuccess ||
       hipMalloc(&h->d_img, (size_t)IMG_BYTES * h->n_obj) != hipSuccess ||
@@ -631,17 +681,26 @@ tg_status tg_nsdf_query(tg_nsdf* h, const float* params, const int64_t* offsets,
   if (!h) return TG_ERR_INVALID_ARGUMENT;
   if (!params || !offsets || !out || !xhat) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query: null pointer");
   if (max_count < 0) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query: max_count < 0");
-  hipStream_t s = (hipStream_t)stream;
-  hipLaunchKernelGGL(nsdf_pack_kernel, dim3((IMG_WORDS + 255) / 256, h->n_obj), dim3(256), 0, s, params, h->n_obj,
-                     h->d_img);
-  if (max_count > 0) {
-    const int64_t per_block = 4 * 16 * QUERY_TILES_PER_WAVE;
-    const dim3 grid((unsigned)((max_count + per_block - 1) / per_block), (unsigned)h->n_obj);
-    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES, s, h->d_img, offsets, xhat, out, grad,
-                       h->d_silu);
-  }
-  const hipError_t e = hipGetLastError();
-  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+  return launch_query(h, h->d_img, params, offsets, max_count, xhat, out, grad, (hipStream_t)stream);
+}
+
+tg_status tg_nsdf_query_noalloc(tg_nsdf* h, const float* params, const int64_t* offsets, int64_t max_count,
+                                const float* xhat, float* out, float* grad, void* stream) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  if (!params || !offsets || !out || !xhat) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query_noalloc: null pointer");
+  if (max_count < 0) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query_noalloc: max_count < 0");
+  if (h->n_obj > TG_NSDF_QUERY_NOALLOC_MAX_OBJECTS)
+    return nfail(h, TG_ERR_INVALID_ARGUMENT,
+                 "query_noalloc: " + std::to_string(h->n_obj) + " objects exceed the static scratch, which holds " +
+                     std::to_string(TG_NSDF_QUERY_NOALLOC_MAX_OBJECTS) + " (use tg_nsdf_query)");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return nfail(h, TG_ERR_HIP, "query_noalloc: hipGetDevice failed");
+  if (dev != h->device)
+    return nfail(h, TG_ERR_INVALID_ARGUMENT, "query_noalloc: the current device is not the handle's device");
+  uint32_t* img = nullptr;
+  const tg_status st = scratch_addr(h, dev, &img);
+  if (st != TG_OK) return st;
+  return launch_query(h, img, params, offsets, max_count, xhat, out, grad, (hipStream_t)stream);
 }
 
 }  // extern "C"
