@@ -54,8 +54,11 @@ static void encode(const double* x, double* f) {
 
 static double sigm(double z) { return 1.0 / (1.0 + exp(-z)); }
 
-/* Forward for one point; keeps pre-activations z[4][64] and activations a[5][64] (a[0] = features). */
-static double forward1(const double* P, const double* x, double z[4][NS_H], double a[5][NS_H], int bfl) {
+/* Forward for one point; keeps pre-activations z[4][64] and activations a[5][64] (a[0] = features).
+ * zw (or NULL) records each layer sum before its BF16 rounding and sabs the sum of the absolute
+ * values of its terms (bias included): what the rounding of z acted on, and its scale. */
+static double forward1t(const double* P, const double* x, double z[4][NS_H], double a[5][NS_H], int bfl,
+                        double zw[4][NS_H], double sabs[4][NS_H]) {
   const double *W[5], *b[5];
   param_views(P, W, b);
   double f[NS_F];
@@ -64,9 +67,17 @@ static double forward1(const double* P, const double* x, double z[4][NS_H], doub
   int nin = NS_F;
   for (int l = 0; l < 4; ++l) {
     for (int o = 0; o < NS_H; ++o) {
-      double s = 0;
-      for (int i = 0; i < nin; ++i) s += bf(W[l][o * nin + i], bfl) * bf(a[l][i], bfl);
+      double s = 0, sa = 0;
+      for (int i = 0; i < nin; ++i) {
+        const double t = bf(W[l][o * nin + i], bfl) * bf(a[l][i], bfl);
+        s += t;
+        sa += fabs(t);
+      }
       s += b[l][o];
+      if (zw) {
+        zw[l][o] = s;
+        sabs[l][o] = sa + fabs(b[l][o]);
+      }
       s = bf(s, bfl);
       z[l][o] = s;
       a[l + 1][o] = s * sigm(s);
@@ -76,6 +87,30 @@ static double forward1(const double* P, const double* x, double z[4][NS_H], doub
   double out = b[4][0];
   for (int i = 0; i < NS_H; ++i) out += W[4][i] * a[4][i];
   return out;
+}
+
+static double forward1(const double* P, const double* x, double z[4][NS_H], double a[5][NS_H], int bfl) {
+  return forward1t(P, x, z, a, bfl, NULL, NULL);
+}
+
+/* The BF16-rounding record of the forward pass at n points (diagnostics of BF16 rounding ties):
+ * feat[n][48] the encoding features before rounding, zw[n][4][64] the layer sums before rounding,
+ * zb[n][4][64] after it (the pre-activations SiLU sees), sabs[n][4][64] the sum of the absolute
+ * values of each layer sum's terms.  bf16 = 1 is the BF16-emulating network. */
+void or_nsdf_forward_trace(const double* P, int64_t n, const double* x, double* feat, double* zw, double* zb,
+                           double* sabs, int bf16) {
+  for (int64_t s = 0; s < n; ++s) {
+    double z[4][NS_H], a[5][NS_H], w[4][NS_H], sa[4][NS_H];
+    (void)forward1t(P, x + 3 * s, z, a, bf16, w, sa);
+    for (int i = 0; i < NS_F; ++i) feat[s * NS_F + i] = a[0][i];
+    for (int l = 0; l < 4; ++l)
+      for (int o = 0; o < NS_H; ++o) {
+        const int64_t k = (s * 4 + l) * NS_H + o;
+        zw[k] = w[l][o];
+        zb[k] = z[l][o];
+        sabs[k] = sa[l][o];
+      }
+  }
 }
 
 /* out[n] and, if gx != NULL, d out / d x_hat [n][3] (reverse pass through the network).  With

@@ -71,6 +71,8 @@ typedef struct {               /* every array [S][...]; NULL = not produced */
   double* link_sums;           /* [S][11][E][L] */
   double* link_sums_noisy;     /* [S][11][E][L] */
   double* xtalk_scale;         /* [S][6][E][T]: sum_k |C_jk||z_k| of the crosstalk sum */
+  double* xhat;                /* [S][3][E][T]: the network's input x_hat where the neural backend
+                                  evaluated it, NaN elsewhere (a record, for diagnostics) */
 } or_outputs;
 
 typedef struct {

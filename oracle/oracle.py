@@ -15,7 +15,8 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile the oracle (contraction off, no fast-math, OpenMP)."""
-    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "oracle_impl.h", "oracle.h", "nsdf.c", "thermal.c")]
+    srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "oracle_impl.h", "oracle.h", "nsdf.c", "thermal.c",
+                                              "proximity.c")]
     srcs = [s for s in srcs if os.path.exists(s)]
     if not force and os.path.exists(_LIB) and all(os.path.getmtime(_LIB) >= os.path.getmtime(s) for s in srcs):
         return _LIB
@@ -57,7 +58,7 @@ class OrInputs(C.Structure):
 
 class OrOutputs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("bit", "bit_noisy", "depth", "prox", "surfdist", "ft", "ft_noisy",
-                                         "normal", "link_sums", "link_sums_noisy", "xtalk_scale")]
+                                         "normal", "link_sums", "link_sums_noisy", "xtalk_scale", "xhat")]
 
 
 class OrState(C.Structure):
@@ -184,7 +185,8 @@ class Oracle:
                       prox=((S, E, T), np.float64), surfdist=((S, E, T), np.float64),
                       ft=((S, 6, E, T), np.float64), ft_noisy=((S, 6, E, T), np.float64),
                       normal=((S, 3, E, T), np.float64), link_sums=((S, 11, E, L), np.float64),
-                      link_sums_noisy=((S, 11, E, L), np.float64), xtalk_scale=((S, 6, E, T), np.float64))
+                      link_sums_noisy=((S, 11, E, L), np.float64), xtalk_scale=((S, 6, E, T), np.float64),
+                      xhat=((S, 3, E, T), np.float64))
         out = {k: np.zeros(*shapes[k]) for k in want}
         O = OrOutputs(**{k: v.ctypes.data for k, v in out.items()})
         I = OrInputs(ls.ctypes.data, oid.ctypes.data, _ptr(ost), int(inp.step0), S)
@@ -236,6 +238,8 @@ def _nsdf_lib():
                                            C.c_int, C.c_double, C.c_double]
         lib.or_nsdf_loss_grad2.restype = C.c_double
         lib.or_nsdf_dirderiv.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        lib.or_nsdf_forward_trace.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_int]
         lib._nsdf_ready = True
     return lib
 
@@ -272,6 +276,21 @@ def nsdf_loss_grad(P, x, target, bf16=False, pair_lambda=0.0, gtarget=None, grad
     loss = lib.or_nsdf_loss_grad2(P.ctypes.data, x.shape[0], x.ctypes.data, t.ctypes.data, _ptr(gt), g.ctypes.data,
                                    int(bf16), float(pair_lambda), float(grad_lambda))
     return loss, g
+
+
+def nsdf_forward_trace(P, x, bf16=True):
+    """The BF16 rounding record of the forward pass at x[n][3]: encoding features before rounding
+    [n][48], layer sums before rounding [n][4][64], after it [n][4][64], and the sum of the
+    absolute values of each layer sum's terms [n][4][64]."""
+    lib = _nsdf_lib()
+    P = np.ascontiguousarray(P, np.float64)
+    x = np.ascontiguousarray(x, np.float64).reshape(-1, 3)
+    n = x.shape[0]
+    feat = np.zeros((n, 48))
+    zw, zb, sabs = np.zeros((n, 4, 64)), np.zeros((n, 4, 64)), np.zeros((n, 4, 64))
+    lib.or_nsdf_forward_trace(P.ctypes.data, n, x.ctypes.data, feat.ctypes.data, zw.ctypes.data, zb.ctypes.data,
+                              sabs.ctypes.data, int(bf16))
+    return feat, zw, zb, sabs
 
 
 def nsdf_dirderiv(P, x, u, bf16=False):
@@ -395,3 +414,49 @@ def thermal_run(th, layout, depth, fields=None, precision="f64"):
             tt.ctypes.data, led.ctypes.data)
     assert rc == 0
     return fields, tt, led
+
+
+# ------------------------------------------------------------------------------------------------
+# ProximityTaxel (proximity.c)
+# ------------------------------------------------------------------------------------------------
+class OrProxProblem(C.Structure):
+    _fields_ = [("num_envs", C.c_int32), ("num_links", C.c_int32), ("num_taxels", C.c_int32),
+                ("num_objects", C.c_int32), ("link_offset", C.c_void_p), ("taxel_pos", C.c_void_p),
+                ("taxel_normal", C.c_void_p), ("taxel_radius", C.c_void_p), ("cloud_offset", C.c_void_p),
+                ("cloud", C.c_void_p), ("k", C.c_double), ("k_s", C.c_double), ("density", C.c_double),
+                ("seed", C.c_uint64), ("radius_rho", C.c_double)]
+
+
+def prox_run(link_offset, taxel_pos, taxel_normal, taxel_radius, clouds, link_state, obj_id, obj_state=None,
+             step0=0, k=300.0, k_s=10.0, density=100.0, seed=0, radius_rho=0.0, gain=None, threads=0):
+    """ProximityTaxel channels in FP64 by brute force over every point (App. A.6).
+    link_state [S][13][E*L], obj_id [S][E], obj_state [S][13][E] or None, clouds: list of [n_o][3]
+    object-frame points.  Returns (ft [S][6][E][T] link frame, mass [S][E][T] = sum_i P_ij)."""
+    lib = _load()
+    if not getattr(lib, "_prox_ready", False):
+        lib.or_prox_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_int]
+        lib._prox_ready = True
+    off = np.ascontiguousarray(link_offset, np.int32)
+    pos = np.ascontiguousarray(taxel_pos, np.float32).reshape(-1, 3)
+    nrm = np.ascontiguousarray(taxel_normal, np.float32).reshape(-1, 3)
+    rad = np.ascontiguousarray(taxel_radius, np.float32).reshape(-1)
+    T, L = pos.shape[0], off.size - 1
+    coff = np.zeros(len(clouds) + 1, np.int32)
+    coff[1:] = np.cumsum([len(c) for c in clouds])
+    cloud = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float32).reshape(-1, 3) for c in clouds])
+                                 if clouds else np.zeros((0, 3), np.float32))
+    ls = np.ascontiguousarray(link_state, np.float32)
+    oid = np.ascontiguousarray(obj_id, np.int32)
+    S, E = oid.shape
+    assert ls.shape == (S, 13, E * L)
+    ost = None if obj_state is None else np.ascontiguousarray(obj_state, np.float32)
+    gn = None if gain is None else np.ascontiguousarray(gain, np.float32).reshape(E, T)
+    Pb = OrProxProblem(E, L, T, len(clouds), off.ctypes.data, pos.ctypes.data, nrm.ctypes.data, rad.ctypes.data,
+                       coff.ctypes.data, cloud.ctypes.data, float(k), float(k_s), float(density), int(seed),
+                       float(radius_rho))
+    ft = np.zeros((S, 6, E, T))
+    mass = np.zeros((S, E, T))
+    lib.or_prox_run(C.byref(Pb), ls.ctypes.data, oid.ctypes.data, _ptr(ost), int(step0), S, _ptr(gn),
+                    ft.ctypes.data, mass.ctypes.data, int(threads or os.cpu_count() or 1))
+    return ft, mass

@@ -60,6 +60,8 @@ typedef struct {
   REAL depth;      /* clean depth d */
   REAL prox, surf;
   REAL f[3], tau[3], mb[3];
+  int nn;          /* the neural backend evaluated the network at xh */
+  double xh[3];
 } SFX(taxel_out);
 
 /* One clean readout: App. A.1 probe transform and SDF depth, ContactDepthProbe,
@@ -149,6 +151,8 @@ static void SFX(readout)(const or_problem* P, const SFX(pose) * L, const SFX(pos
         xh[i] = (double)((qo[i] - c) * (REAL)einv);
       }
       or_nsdf_forward(P->nsdf_params + (int64_t)oid * 15681, 1, xh, &out, gxh, 1);
+      o->nn = 1;
+      for (int i = 0; i < 3; ++i) o->xh[i] = xh[i];
       const REAL phin = (REAL)half * (REAL)out;
       if (!(FABS(phin) < (REAL)P->nsdf_band)) {
         phi = phin;
@@ -364,6 +368,8 @@ int SFX(or_run)(const or_problem* P, const or_inputs* in, or_outputs* out, or_st
         if (out->depth) out->depth[ok] = (double)o->depth;
         if (out->prox) out->prox[ok] = (double)o->prox;
         if (out->surfdist) out->surfdist[ok] = (double)o->surf;
+        if (out->xhat)
+          for (int c = 0; c < 3; ++c) out->xhat[(int64_t)s * 3 * ET + (int64_t)c * ET + k] = o->nn ? o->xh[c] : NAN;
         for (int c = 0; c < 3; ++c) {
           if (out->ft) {
             out->ft[(int64_t)s * 6 * ET + (int64_t)c * ET + k] = (double)o->f[c];
