@@ -1,0 +1,122 @@
+"""Pins of the spectral TemperatureGrid oracle (App. D.1: spectral diffusion, T^4 radiation,
+convection, sensor element lag) against closed forms.
+
+- A product of cosines that satisfies the zero-flux walls, cos(pi m (i + 1/2) / n) per axis, is an
+  eigenvector of the mirror-padded FFT step: one step multiplies it by exactly
+  1 / (1 + alpha dt k^2) with k^2 = (pi / (n dx))^2 (m_x^2 + m_y^2 + m_z^2).  Periodic instead of
+  mirrored padding, or the wavenumbers of the unpadded grid, fail it.
+- The mean of any field is kept (zero flux), and many steps approach the continuous decay
+  exp(-alpha k^2 t) of the mode.
+- A uniform field loses, per exposed face, dt (eps sigma (T_K^4 - T_amb,K^4) + h (T - T_amb)) /
+  (rho c_p dx) in one step (kelvin in the T^4 law, a per-volume rate through the face).
+- The measured reading of a voxel held at T_v follows T_v + (T_0 - T_v) (1 - dt / tau)^k.
+- Contact conduction into a top voxel: kappa d (T_obj - T), with the explicit solver's kappa.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import thermal_spectral as TS
+from paper_2606_22332_amd import synth
+
+
+def cos_mode(n, m):
+    i = np.arange(n) + 0.5
+    c = [np.cos(np.pi * mm * i / n) for mm in m]          # (mz, my, mx)
+    return c[0][:, None, None] * c[1][None, :, None] * c[2][None, None, :]
+
+
+@pytest.mark.parametrize("m", [(0, 0, 1), (1, 2, 0), (3, 1, 5), (15, 0, 7)])
+def test_cosine_mode_is_an_eigenvector(m):
+    n, dx, alpha, dt = 16, 1e-3, 1e-7, 0.05
+    T = 22.0 + cos_mode(n, m)
+    out = TS.spectral_diffusion(T, alpha, dt, dx)
+    k2 = (np.pi / (n * dx)) ** 2 * sum(mm * mm for mm in m)
+    want = 22.0 + cos_mode(n, m) / (1.0 + alpha * dt * k2)
+    np.testing.assert_allclose(out, want, rtol=0, atol=1e-12)
+
+
+def test_mean_is_kept_and_the_continuum_decay_is_approached():
+    rng = np.random.default_rng(3)
+    n, dx, alpha = 16, 1e-3, 1e-7
+    T = 30.0 + rng.normal(0, 2, (n, n, n))
+    out = TS.spectral_diffusion(T, alpha, 0.5, dx)
+    assert out.mean() == pytest.approx(T.mean(), abs=1e-12)
+    assert np.var(out) < np.var(T)
+    # implicit steps of the slowest mode over t = 20 s tend to exp(-alpha k^2 t) as dt shrinks
+    k2 = (np.pi / (n * dx)) ** 2
+    t = 20.0
+    errs = []
+    for steps in (10, 100):
+        F = cos_mode(n, (0, 0, 1))
+        for _ in range(steps):
+            F = TS.spectral_diffusion(F, alpha, t / steps, dx)
+        errs.append(abs(F[0, 0, 0] / cos_mode(n, (0, 0, 1))[0, 0, 0] - np.exp(-alpha * k2 * t)))
+    assert errs[1] < 0.2 * errs[0] and errs[1] < 1e-4
+
+
+def test_unconditionally_stable():
+    rng = np.random.default_rng(4)
+    T = 25.0 + rng.normal(0, 5, (16, 16, 16))
+    out = TS.spectral_diffusion(T, 1e-7, 1e6, 1e-3)            # alpha dt / dx^2 = 1e5
+    assert np.abs(out - T.mean()).max() < 1e-3 * np.abs(T - T.mean()).max()
+
+
+def scene_th(E=2, P_gen=0.0, emissivity=0.85, T0=40.0, dt=1e-3, T_obj=(50.0, 15.0)):
+    sc = synth.make_scene("c5", num_envs=E, num_steps=1)
+    th = sc.thermal
+    th.P_gen, th.emissivity, th.T0, th.dt = P_gen, emissivity, T0, dt
+    th.T_obj = np.asarray(T_obj[:E], np.float32)
+    return sc, th
+
+
+def test_uniform_field_loses_radiation_and_convection_per_exposed_face():
+    sc, th = scene_th(E=1)
+    h = 8.0
+    depth = np.zeros((1, 1, sc.layout.num_taxels))
+    fields, _ = TS.spectral_run(th, sc.layout, depth, h_conv=h)
+    T = float(np.float32(th.T0))
+    q = float(np.float32(th.emissivity)) * TS.SIGMA_SB * ((T + 273.15) ** 4 - (22.0 + 273.15) ** 4) + h * (T - 22.0)
+    dxf, rc, dtf = float(np.float32(th.dx)), float(np.float32(th.rho_cp)), float(np.float32(th.dt))
+    faces = TS.surface_faces(th.n)
+    want = T - dtf * faces * q / (rc * dxf)
+    np.testing.assert_allclose(fields[0, 0], want, rtol=0, atol=1e-12)
+    assert fields[0, 0][8, 8, 8] == pytest.approx(T, abs=1e-12)                 # interior: no loss
+    assert (T - fields[0, 0][0, 0, 0]) == pytest.approx(3 * (T - fields[0, 0][0, 8, 8]), rel=1e-9)
+
+
+def test_sensor_lag_step_response():
+    sc, th = scene_th(E=1, emissivity=0.0, T0=22.0)
+    th.T_amb = 22.0
+    S, tau = 12, 0.004
+    depth = np.zeros((S, 1, sc.layout.num_taxels))
+    fields = np.full((1, len(th.field_links), th.n, th.n, th.n), 35.0)       # voxels held at 35 (no sources)
+    t_meas = np.full((1, sc.layout.num_taxels), 22.0)
+    _, out = TS.spectral_run(th, sc.layout, depth, fields=fields, tau=tau, t_meas=t_meas)
+    l = th.field_links[0]
+    j = sc.layout.link_offset[l]
+    r = float(np.float32(th.dt)) / tau
+    want = 35.0 + (22.0 - 35.0) * (1 - r) ** np.arange(1, S + 1)
+    np.testing.assert_allclose(out[:, 0, j], want, rtol=0, atol=1e-9)
+    # without lag the reading is the voxel itself
+    _, raw = TS.spectral_run(th, sc.layout, depth[:1], fields=np.full_like(fields, 35.0))
+    assert raw[0, 0, j] == pytest.approx(35.0, abs=1e-12)
+
+
+def test_contact_conduction_into_the_top_voxel():
+    sc, th = scene_th(E=1, emissivity=0.0, T0=22.0, T_obj=(50.0,))
+    K = oracle.thermal_constants(th)
+    l = th.field_links[0]
+    j = sc.layout.link_offset[l]
+    depth = np.zeros((1, 1, sc.layout.num_taxels))
+    depth[0, 0, j] = 1e-3
+    fields, _ = TS.spectral_run(th, sc.layout, depth)
+    v = oracle.thermal_voxel(th, sc.layout.pos[j])
+    top = fields[0, 0][th.n - 1].reshape(-1)
+    others = sum(1 for jj in range(sc.layout.link_offset[l], sc.layout.link_offset[l + 1])
+                 if jj != j and oracle.thermal_voxel(th, sc.layout.pos[jj]) == v)
+    assert others == 0
+    assert top[v] == pytest.approx(22.0 + K["kappa"] * 1e-3 * (50.0 - 22.0), rel=1e-12)
+    mask = np.ones(th.n * th.n, bool)
+    mask[v] = False
+    np.testing.assert_allclose(top[mask], 22.0, atol=1e-12)
