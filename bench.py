@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "taxel-readouts/sec on 1 MI355X (grid-SDF vs neural-SDF at ≤0.5 mm depth err)"
+# weight of the network training's L1 term on its input gradient (0: value-only recipe)
+DEFAULT_GRAD_LAMBDA = 0.005
 HBM_PEAK_GBS = 8000.0
 
 
@@ -41,33 +43,47 @@ def algorithmic_bytes(E, L, T, S, n_obj, grid_n, noisy=True, sums=True):
     return R * per_readout + state + inputs + link + grids, R
 
 
-def cpu_baseline(sc, inp, target_s=12.0):
-    """The oracle as it stands (FP32 parity build, OpenMP over envs) on a bounded sample of
-    envs of the same workload, all steps; scaled to readouts/s."""
+def _oracle_rate(sc, inp, precision, threads, target_s, n0):
+    """Readouts/s of the oracle over a sample of envs (all steps), grown until it takes about
+    target_s (at most three rounds); returns (rate, envs in the sample, seconds)."""
     import oracle
     from paper_2606_22332_amd import synth
-    threads = os.cpu_count() or 1
     L, T = sc.layout.num_links, sc.layout.num_taxels
-    n = max(threads, 8)
-    t0 = time.perf_counter()
+    want = ("bit", "bit_noisy", "depth", "prox", "ft", "ft_noisy", "link_sums", "link_sums_noisy")
+    n = n0
     envs = np.arange(n)
-    oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision="f32", threads=threads,
-                       want=("bit", "bit_noisy", "depth", "prox", "ft", "ft_noisy", "link_sums", "link_sums_noisy"))
+    t0 = time.perf_counter()
+    oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision=precision, threads=threads, want=want)
     dt = time.perf_counter() - t0
-    for _ in range(3):   # grow the sample until it takes about target_s (at most three rounds)
+    for _ in range(3):
         if dt >= target_s / 2 or n >= sc.num_envs:
             break
         n2 = int(min(sc.num_envs, max(n + 1, n * target_s / max(dt, 1e-3))))
         envs = np.linspace(0, sc.num_envs - 1, n2).astype(np.int64)
         t0 = time.perf_counter()
-        oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision="f32", threads=threads,
-                           want=("bit", "bit_noisy", "depth", "prox", "ft", "ft_noisy", "link_sums",
-                                 "link_sums_noisy"))
+        oracle.run_readout(sc, synth.subset_envs(inp, envs, L), envs=envs, precision=precision, threads=threads,
+                           want=want)
         dt = time.perf_counter() - t0
         n = n2
     S = inp.link_state.shape[0]
-    return {"value": n * T * S / dt, "unit": "taxel-readouts/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} of {sc.num_envs} envs x {T} taxels x {S} steps ({dt:.1f} s, FP32 oracle)"}
+    return n * T * S / dt, n, dt
+
+
+def cpu_baseline(sc, inp, target_s=12.0):
+    """The oracle as it stands (OpenMP over envs) on bounded samples of envs of the same workload,
+    all steps, scaled to readouts/s: the FP32 parity build on every host thread (the reported
+    value), the FP64 build on every thread, and the FP32 build on one thread."""
+    threads = os.cpu_count() or 1
+    T, S = sc.layout.num_taxels, inp.link_state.shape[0]
+    v, n, dt = _oracle_rate(sc, inp, "f32", threads, target_s, max(threads, 8))
+    v64, n64, dt64 = _oracle_rate(sc, inp, "f64", threads, target_s / 2, max(threads, 8))
+    v1, n1, dt1 = _oracle_rate(sc, inp, "f32", 1, target_s / 3, 2)
+    return {"value": v, "unit": "taxel-readouts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} of {sc.num_envs} envs x {T} taxels x {S} steps ({dt:.1f} s, FP32 oracle)",
+            "fp64": {"value": v64, "cores": threads,
+                     "sample": f"{n64} envs x {T} taxels x {S} steps ({dt64:.1f} s, FP64 oracle)"},
+            "one_thread": {"value": v1, "cores": 1,
+                           "sample": f"{n1} envs x {T} taxels x {S} steps ({dt1:.1f} s, FP32 oracle)"}}
 
 
 def fp64_error(sc, inp, out, envs):
@@ -208,11 +224,16 @@ def bench_c4(args) -> dict:
         pts = synth.nsdf_points(sc.grids, args.nsdf_samples, seed=sc.geom_seed + 7)
     gen_s = time.perf_counter() - t0
     ns = B.Nsdf(sc.grids)
-    rec = ns.targets(torch.from_numpy(pts).cuda())
+    grec = None
+    if args.grad_lambda > 0:   # gradient records: the grid's gradient, target of the gradient term
+        rec, grec = ns.targets(torch.from_numpy(pts).cuda(), grad=True)
+    else:
+        rec = ns.targets(torch.from_numpy(pts).cuda())
     del pts
     P = torch.from_numpy(synth.nsdf_init(n_obj, sc.geom_seed + 8)).cuda()
     m, v = torch.zeros_like(P), torch.zeros_like(P)
-    hp = B.train_params(lr=1e-3, batch=1 << 14, seed=sc.geom_seed + 9, pair_lambda=args.pair_lambda)
+    hp = B.train_params(lr=1e-3, batch=1 << 14, seed=sc.geom_seed + 9, pair_lambda=args.pair_lambda,
+                        grad_lambda=args.grad_lambda)
     loss = torch.zeros((args.train_steps, n_obj), device="cuda")
     torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -227,10 +248,12 @@ def bench_c4(args) -> dict:
             if n_i <= 0:
                 continue
             lr_i = 1e-5 + 0.5 * (1e-3 - 1e-5) * (1.0 + np.cos(np.pi * (i + 0.5) / pieces))
-            hp_i = B.train_params(lr=float(lr_i), batch=1 << 14, seed=sc.geom_seed + 9, pair_lambda=args.pair_lambda)
-            ns.train(P, m, v, rec, int(edges[i]), n_i, hp_i, loss=loss[int(edges[i]):int(edges[i + 1])])
+            hp_i = B.train_params(lr=float(lr_i), batch=1 << 14, seed=sc.geom_seed + 9, pair_lambda=args.pair_lambda,
+                                  grad_lambda=args.grad_lambda)
+            ns.train(P, m, v, rec, int(edges[i]), n_i, hp_i, loss=loss[int(edges[i]):int(edges[i + 1])],
+                     grad_samples=grec)
     else:
-        ns.train(P, m, v, rec, 0, args.train_steps, hp, loss=loss)
+        ns.train(P, m, v, rec, 0, args.train_steps, hp, loss=loss, grad_samples=grec)
     b.record()
     torch.cuda.synchronize()
     train_ms = a.elapsed_time(b)
@@ -238,7 +261,7 @@ def bench_c4(args) -> dict:
     half = torch.tensor([0.5 * (g.n - 1) * float(g.spacing) for g in sc.grids], device="cuda")
     loss_um = (final_loss * half * 1e6).cpu().numpy()
     ns.close()
-    del rec
+    del rec, grec
     mask = (B.TG_OUT_BITS | B.TG_OUT_DEPTH | B.TG_OUT_PROX | B.TG_OUT_FT | B.TG_OUT_NORMAL | B.TG_OUT_LINK_SUMS
             | B.TG_OUT_SURFDIST)
     d = B.to_device(inp)
@@ -297,6 +320,7 @@ def bench_c4(args) -> dict:
                                                 "p99": q99(ang[net])}},
         "training": {"steps": args.train_steps, "batch_per_object": 1 << 14, "samples_per_object": args.nsdf_samples,
                      "lr_schedule": args.lr_schedule, "pair_lambda": args.pair_lambda,
+                     "grad_lambda": args.grad_lambda,
                      "pair_delta_m": args.pair_delta if args.pair_lambda > 0 else None,
                      "ms_total": train_ms, "ms_per_step": train_ms / args.train_steps,
                      "final_l1_um_median": float(np.median(loss_um)), "final_l1_um_max": float(loss_um.max())},
@@ -305,6 +329,110 @@ def bench_c4(args) -> dict:
                       "network_images": n_obj * 65024 / 1e6},
         "input_gen_s": gen_s,
     }
+
+
+def bench_c2_step(reps: int = 3) -> dict:
+    """The per-step entry point on the 4096-env x 200-taxel noisy hand (16 links, banded
+    crosstalk): 100 consecutive tg_readout_step calls, each one launch that reads and writes the
+    noise state, timed with HIP events on the stream they run on (median per step over `reps`
+    runs of 100 steps), beside the same 100 steps as one rollout launch."""
+    import torch
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+    sc = synth.make_scene("c2")
+    inp = synth.make_inputs(sc)
+    E, L, T, S = sc.num_envs, sc.layout.num_links, sc.layout.num_taxels, inp.link_state.shape[0]
+    mask = B.TG_OUT_BITS | B.TG_OUT_DEPTH | B.TG_OUT_PROX | B.TG_OUT_FT | B.TG_OUT_LINK_SUMS | B.TG_OUT_NOISY
+    ro = B.Readout(sc, mask)
+    d = B.to_device(inp)
+    ro.alloc_outputs(S)
+    stream = torch.cuda.current_stream()
+    for s_ in range(S):          # warm-up (graph recorded, then updated per call)
+        ro.step(d, s_)
+    torch.cuda.synchronize()
+    per_step, walls = [], []
+    for _ in range(reps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(S + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev[0].record(stream)
+        for s_ in range(S):
+            ro.step(d, s_)
+            ev[s_ + 1].record(stream)
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t0) / S * 1e3)
+        per_step += [ev[i].elapsed_time(ev[i + 1]) for i in range(S)]
+    ro.reset(None, 0)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ro.rollout(d, S)
+    e0.record(stream)
+    ro.rollout(d, S)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    roll_ms = e0.elapsed_time(e1)
+    ro.close()
+    ms = float(np.median(per_step))
+    nbytes, _ = algorithmic_bytes(E, L, T, 1, len(sc.grids), sc.grids[0].n, True, True)
+    return {"workload": f"c2: {E} envs x {T} taxels ({L} links), noisy, banded crosstalk; per-step tg_readout_step",
+            "ms_per_step_median": ms, "ms_per_step_min": float(np.min(per_step)),
+            "host_wall_ms_per_step": float(np.median(walls)), "readouts_per_s": E * T / (ms * 1e-3),
+            "algorithmic_bytes_per_step": nbytes, "hbm_frac": nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "rollout_ms_per_step": roll_ms / S}
+
+
+def bench_prox(reps: int = 5) -> dict:
+    """The ProximityTaxel readout (App. A.6) on the 4096-env x 200-taxel hand: 8 objects, each
+    tracked by 5000 area-uniform surface points, sensing radius 1 cm, k = 300, k_s = 10,
+    density 100; one 100-step launch timed with HIP events (median of `reps`), with the error of
+    sampled envs against the FP64 oracle."""
+    import torch
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+    sc = synth.make_scene("c2")
+    inp = synth.make_inputs(sc)
+    clouds = synth.surface_clouds(sc.grids, 5000, seed=sc.geom_seed + 20)
+    E, T, S = sc.num_envs, sc.layout.num_taxels, inp.link_state.shape[0]
+    px = B.Proximity(sc, clouds)
+    d = B.to_device(inp)
+    stream = torch.cuda.current_stream()
+    ft, mass = px.rollout(d)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        px.rollout(d, ft=ft, want_mass=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    res = {"workload": f"c2 hand: {E} envs x {T} taxels x {S} steps, ProximityTaxel, 8 objects x 5000 surface "
+                       "points, R = 1 cm", "ms_per_rollout": ms, "readouts_per_s": E * T * S / (ms * 1e-3),
+           "in_range_fraction": float((mass > 0).float().mean().item()),
+           "mean_penetration_sum_m": float(mass[mass > 0].mean().item())}
+    try:
+        import oracle
+        envs = np.array([0, E // 2, E - 1])
+        idx = torch.as_tensor(envs, device="cuda")
+        g = ft[:, :, idx].cpu().numpy()
+        sub = synth.subset_envs(inp, envs, sc.layout.num_links)
+        r, m = oracle.prox_run(sc.layout.link_offset, sc.layout.pos, sc.layout.normal,
+                               np.full(T, 0.01, np.float32), clouds, sub.link_state, sub.obj_id, sub.obj_state,
+                               sub.step0)
+        scale = np.maximum(np.abs(r).max(1, keepdims=True), 1e-9)
+        res["fp64_error"] = {"envs": envs.tolist(), "max_rel_to_channel_max": float((np.abs(g - r) / scale).max())}
+    except ImportError:
+        pass
+    px.close()
+    return res
+
+
+def c4_summary(r: dict) -> dict:
+    """The grid-vs-neural comparison of bench_c4, without the fields of a bench line."""
+    keep = ("config", "grid_path", "speedup_vs_grid", "depth_err_um", "normal_err_deg", "training", "memory_MB")
+    out = {k: r[k] for k in keep}
+    out["neural_path"] = {"ms_per_rollout": r["ms_per_step"], "readouts_per_s": r["value"]}
+    return out
 
 
 def main():
@@ -319,13 +447,17 @@ def main():
     ap.add_argument("--readouts-per-block", type=int, default=0,
                     help="fix the work plan instead of autotuning (the profiles pin the autotuner's choice)")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", default="readout", choices=["readout", "c4"])
+    ap.add_argument("--workload", default="readout", choices=["readout", "c4", "proximity"])
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--nsdf-samples", type=int, default=1 << 17)
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"])
     ap.add_argument("--pair-lambda", type=float, default=0.0,
                     help="weight of the pair term of the training loss (0: the plain L1 recipe)")
     ap.add_argument("--pair-delta", type=float, default=5e-4, help="distance between the points of a pair [m]")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the per-step C2 timing and the C4 grid-vs-neural comparison in the readout run")
+    ap.add_argument("--grad-lambda", type=float, default=None,
+                    help="weight of the L1 term on the network's input gradient against the grid's (0: off)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -336,8 +468,13 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.grad_lambda is None:
+        args.grad_lambda = DEFAULT_GRAD_LAMBDA
     if args.workload == "c4":
         print(json.dumps(bench_c4(args)), flush=True)
+        return
+    if args.workload == "proximity":
+        print(json.dumps(bench_prox()), flush=True)
         return
 
     import torch
@@ -424,8 +561,21 @@ def main():
         idx = torch.as_tensor(envs, device="cuda")
         sub = {k: (v[:, idx] if v.ndim == 3 else v[:, :, idx]).cpu().numpy() for k, v in ro.out.items()}
         rec["fp64_error"] = fp64_error(sc, inp, sub, envs)
-    print(json.dumps(rec), flush=True)
+    ro.out = {}
     ro.close()
+    del dinp
+    torch.cuda.empty_cache()
+    if not args.no_extra and args.config == "c3" and args.envs is None:
+        # the other two lines of the metric: the per-step entry point (C2) and the neural SDF
+        # against the grid (C4: 256 objects, networks trained here on the GPU)
+        rec["c2_step"] = bench_c2_step()
+        torch.cuda.empty_cache()
+        rec["proximity"] = bench_prox()
+        torch.cuda.empty_cache()
+        a4 = argparse.Namespace(**vars(args))
+        a4.envs, a4.steps = None, 5
+        rec["c4_grid_vs_neural"] = c4_summary(bench_c4(a4))
+    print(json.dumps(rec), flush=True)
 
 
 if __name__ == "__main__":

@@ -125,6 +125,18 @@ typedef struct {
   float T0, T_amb;               /* initial (at reset) and ambient temperature [degC]     */
   float P_gen;                   /* internal generation per block [W]                     */
   const float* T_obj;            /* host [num_envs] object temperature [degC]; copied     */
+  /* solver 1: the paper's own step (App. D.1) instead of the explicit one above.  Per step, in
+   * its order: semi-implicit spectral diffusion with zero-flux walls (every mode of the block's
+   * mirror extension divided by 1 + alpha dt k^2), the generation, contact conduction as above,
+   * then grey-body radiation eps sigma (T_K^4 - T_amb,K^4) and convection h_conv (T - T_amb) per
+   * exposed face (divided by rho c_p dx), and the reported temperature passes the sensor
+   * element lag T_meas += dt / lag_tau (T - T_meas) (lag_tau <= 0: no lag; the lag state is part
+   * of the handle's state, reset to T0).  The diffusion is unconditionally stable; create returns
+   * TG_ERR_UNSTABLE unless kappa d_max m <= 1 and 3 (4 eps sigma (T_amb,K + 100)^3 + h_conv) dt /
+   * (rho c_p dx) <= 1, and TG_ERR_UNSUPPORTED for a lag on a link of more than 256 taxels. */
+  int32_t solver;                /* 0 explicit (default), 1 the paper's spectral step    */
+  float h_conv;                  /* convection coefficient [W/m^2K] (solver 1)            */
+  float lag_tau;                 /* sensor element time constant [s] (solver 1)           */
 } tg_thermal_desc;
 
 typedef struct {
@@ -233,11 +245,16 @@ tg_status tg_readout_launch_shape(const tg_readout* h, int32_t* envs_per_block, 
  * instead, so a caller can capture rollout into its own graph. */
 tg_status tg_readout_set_graph(tg_readout* h, int32_t enable);
 
-/* Autotuner for the readout kernel's work plan (readouts per workgroup: 192, 256, 384, 512).
- * Runs each candidate on the caller's inputs and outputs for n_steps steps, keeps the
- * fastest plan for this handle and reports it.  Unlike step/rollout it allocates a state
- * buffer, synchronises and overwrites `out`; the dynamic state is restored afterwards.  The
- * neural backend has no plan to tune (best_target = 0). */
+/* Autotuner for the readout kernel's work plan: readouts per workgroup 128, 192, 256, 320, 384,
+ * 448, 512 (one link per workgroup, so this sets the envs per workgroup and with them the waves
+ * per workgroup).  Runs each candidate on the caller's inputs and outputs for n_steps steps,
+ * keeps the fastest plan for this handle and reports it.  Unlike step/rollout it allocates a
+ * state buffer, synchronises and overwrites `out`; the dynamic state is restored afterwards.
+ * The result is cached for the process under a hash of the configuration (sizes, link layout,
+ * grid sizes, noise kernel variant, output mask, backend, thermal fields), n_steps and whether
+ * objects move: a later call with the same key, on any handle, applies the cached plan without
+ * timing and touches neither `out` nor the state.  The neural backend has no plan to tune
+ * (best_target = 0). */
 tg_status tg_readout_autotune(tg_readout* h, const tg_step_inputs* in, const tg_step_outputs* out, int32_t n_steps,
                               void* hip_stream, int32_t* best_target, float* best_ms);
 

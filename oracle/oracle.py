@@ -428,14 +428,16 @@ class OrProxProblem(C.Structure):
 
 
 def prox_run(link_offset, taxel_pos, taxel_normal, taxel_radius, clouds, link_state, obj_id, obj_state=None,
-             step0=0, k=300.0, k_s=10.0, density=100.0, seed=0, radius_rho=0.0, gain=None, threads=0):
+             step0=0, k=300.0, k_s=10.0, density=100.0, seed=0, radius_rho=0.0, gain=None, threads=0,
+             with_count=False):
     """ProximityTaxel channels in FP64 by brute force over every point (App. A.6).
     link_state [S][13][E*L], obj_id [S][E], obj_state [S][13][E] or None, clouds: list of [n_o][3]
-    object-frame points.  Returns (ft [S][6][E][T] link frame, mass [S][E][T] = sum_i P_ij)."""
+    object-frame points.  Returns (ft [S][6][E][T] link frame, mass [S][E][T] = sum_i P_ij), and
+    with with_count the number of points inside each sphere [S][E][T] as a third value."""
     lib = _load()
     if not getattr(lib, "_prox_ready", False):
         lib.or_prox_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
-                                    C.c_void_p, C.c_void_p, C.c_int]
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         lib._prox_ready = True
     off = np.ascontiguousarray(link_offset, np.int32)
     pos = np.ascontiguousarray(taxel_pos, np.float32).reshape(-1, 3)
@@ -457,6 +459,7 @@ def prox_run(link_offset, taxel_pos, taxel_normal, taxel_radius, clouds, link_st
                        float(radius_rho))
     ft = np.zeros((S, 6, E, T))
     mass = np.zeros((S, E, T))
+    cnt = np.zeros((S, E, T)) if with_count else None
     lib.or_prox_run(C.byref(Pb), ls.ctypes.data, oid.ctypes.data, _ptr(ost), int(step0), S, _ptr(gn),
-                    ft.ctypes.data, mass.ctypes.data, int(threads or os.cpu_count() or 1))
-    return ft, mass
+                    ft.ctypes.data, mass.ctypes.data, _ptr(cnt), int(threads or os.cpu_count() or 1))
+    return (ft, mass, cnt) if with_count else (ft, mass)

@@ -53,9 +53,10 @@ static void cross(const double a[3], const double b[3], double c[3]) {
 
 /* link_state [S][13][E*L] (px py pz qw qx qy qz vx vy vz wx wy wz), obj_id [S][E],
  * obj_state [S][13][E] or NULL (object static at the origin), gain [E][T] or NULL.
- * ft [S][6][E][T] (fx fy fz tx ty tz, link frame); mass [S][E][T] or NULL: sum_i P_ij. */
+ * ft [S][6][E][T] (fx fy fz tx ty tz, link frame); mass [S][E][T] or NULL: sum_i P_ij;
+ * count [S][E][T] or NULL: the number of points inside the sphere (a record for error bounds). */
 void or_prox_run(const or_prox_problem* P, const float* link_state, const int32_t* obj_id, const float* obj_state,
-                 int64_t step0, int32_t S, const float* gain, double* ft, double* mass, int threads) {
+                 int64_t step0, int32_t S, const float* gain, double* ft, double* mass, double* count, int threads) {
   const int E = P->num_envs, L = P->num_links, T = P->num_taxels;
   const int64_t ET = (int64_t)E * T, EL = (int64_t)E * L;
   const uint32_t key[2] = {(uint32_t)P->seed, (uint32_t)(P->seed >> 32)};
@@ -109,7 +110,7 @@ void or_prox_run(const or_prox_problem* P, const float* link_state, const int32_
           for (int i = 0; i < 3; ++i) qL[i] = q[i] - pL[i];
           cross(wL, qL, vtax);
           for (int i = 0; i < 3; ++i) vtax[i] += vL[i];
-          double f[3] = {0, 0, 0}, tau[3] = {0, 0, 0}, msum = 0;
+          double f[3] = {0, 0, 0}, tau[3] = {0, 0, 0}, msum = 0, cnt = 0;
           for (int64_t i = n0; i < n1; ++i) {
             double p[3];
             for (int r = 0; r < 3; ++r) {
@@ -138,6 +139,7 @@ void or_prox_run(const or_prox_problem* P, const float* link_state, const int32_
               tau[c] += P->k * rho * Pij * rxa[c];
             }
             msum += Pij;
+            cnt += 1;
           }
           const double gj = gain ? (double)gain[(int64_t)e * T + j] : 1.0;
           for (int r = 0; r < 3; ++r) {   /* link frame: R_L^T f, R_L^T tau */
@@ -151,6 +153,7 @@ void or_prox_run(const or_prox_problem* P, const float* link_state, const int32_
             ft[((int64_t)s * 6 + 3 + r) * ET + k] = gj * tl;
           }
           if (mass) mass[(int64_t)s * ET + (int64_t)e * T + j] = msum;
+          if (count) count[(int64_t)s * ET + (int64_t)e * T + j] = cnt;
         }
       }
     }

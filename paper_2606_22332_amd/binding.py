@@ -47,7 +47,8 @@ class TgThermalDesc(C.Structure):
     _fields_ = [("num_fields", C.c_int32), ("field_links", C.c_void_p), ("n", C.c_int32), ("dx", C.c_float),
                 ("origin", C.c_float * 3), ("dt", C.c_float), ("k_sensor", C.c_float), ("rho_cp", C.c_float),
                 ("emissivity", C.c_float), ("k_object", C.c_float), ("d_w", C.c_float), ("T0", C.c_float),
-                ("T_amb", C.c_float), ("P_gen", C.c_float), ("T_obj", C.c_void_p)]
+                ("T_amb", C.c_float), ("P_gen", C.c_float), ("T_obj", C.c_void_p), ("solver", C.c_int32),
+                ("h_conv", C.c_float), ("lag_tau", C.c_float)]
 
 
 class TgReadoutConfig(C.Structure):
@@ -169,6 +170,7 @@ def make_config(scene, output_mask: int = OUT_ALL, keep: Optional[list] = None, 
         td.dt, td.k_sensor, td.rho_cp, td.emissivity = th.dt, th.k_sensor, th.rho_cp, th.emissivity
         td.k_object, td.d_w, td.T0, td.T_amb, td.P_gen = th.k_object, th.d_w, th.T0, th.T_amb, th.P_gen
         td.T_obj = tobj.ctypes.data
+        td.solver, td.h_conv, td.lag_tau = int(th.solver), float(th.h_conv), float(th.lag_tau)
         keep += [links, tobj, td]
         cfg.thermal = C.addressof(td)
         cfg.output_mask |= TG_OUT_TEMP
@@ -350,7 +352,10 @@ class Readout:
         buf = torch.empty(self.state_size(), dtype=torch.uint8, device=self.device)
         self.get_state(buf)
         nb = self.E * len(th.field_links) * 16 ** 3 * 4
-        return buf[-nb:].view(torch.float32).reshape(self.E, len(th.field_links), 16, 16, 16).clone()
+        # the fields end the state, but for the sensor-lag readings [E][T] of the spectral solver
+        tail = self.E * self.T * 4 if getattr(th, "solver", 0) == 1 and getattr(th, "lag_tau", 0.0) > 0 else 0
+        end = buf.numel() - tail
+        return buf[end - nb:end].view(torch.float32).reshape(self.E, len(th.field_links), 16, 16, 16).clone()
 
 
 def unpack_bits(words: np.ndarray, T: int) -> np.ndarray:
@@ -371,7 +376,7 @@ class TgNsdfConfig(C.Structure):
 
 class TgNsdfTrainParams(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
-                ("batch", C.c_int32), ("seed", C.c_uint64), ("pair_lambda", C.c_float)]
+                ("batch", C.c_int32), ("seed", C.c_uint64), ("pair_lambda", C.c_float), ("grad_lambda", C.c_float)]
 
 
 _nsdf_ready = False
@@ -386,12 +391,13 @@ def _nsdf_lib() -> C.CDLL:
             "tg_nsdf_create": ([P, P], C.c_int),
             "tg_nsdf_destroy": ([P], C.c_int),
             "tg_nsdf_last_error": ([P], C.c_char_p),
-            "tg_nsdf_targets": ([P, P, I64, P, P], C.c_int),
-            "tg_nsdf_grad": ([P, P, P, I64, C.c_float, P, P, P], C.c_int),
+            "tg_nsdf_targets": ([P, P, I64, P, P, P], C.c_int),
+            "tg_nsdf_grad": ([P, P, P, P, I64, C.c_float, C.c_float, P, P, P], C.c_int),
             "tg_nsdf_adam": ([P, P, P, P, I64, I64, P, P], C.c_int),
-            "tg_nsdf_train": ([P, P, P, P, P, I64, I64, C.c_int32, P, P, P], C.c_int),
+            "tg_nsdf_train": ([P, P, P, P, P, P, I64, I64, C.c_int32, P, P, P], C.c_int),
             "tg_nsdf_query": ([P, P, P, I64, P, P, P, P], C.c_int),
             "tg_nsdf_query_noalloc": ([P, P, P, I64, P, P, P, P], C.c_int),
+            "tg_nsdf_query_trace": ([P, P, P, I64, P, P, P, P, P], C.c_int),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -402,8 +408,8 @@ def _nsdf_lib() -> C.CDLL:
 
 
 def train_params(lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, batch=16384, seed=0,
-                 pair_lambda=0.0) -> TgNsdfTrainParams:
-    return TgNsdfTrainParams(lr, beta1, beta2, eps, batch, seed, pair_lambda)
+                 pair_lambda=0.0, grad_lambda=0.0) -> TgNsdfTrainParams:
+    return TgNsdfTrainParams(lr, beta1, beta2, eps, batch, seed, pair_lambda, grad_lambda)
 
 
 class Nsdf:
@@ -436,35 +442,41 @@ class Nsdf:
             raise TgError(f"{what}: {self.lib.tg_status_string(rc).decode()}: "
                           f"{self.lib.tg_nsdf_last_error(self.h).decode()}")
 
-    def targets(self, points, samples=None, stream=None):
-        """points: float32 [n_obj, n, 3] object-frame positions -> float32 [n_obj, n, 4] records."""
+    def targets(self, points, samples=None, stream=None, grad=False):
+        """points: float32 [n_obj, n, 3] object-frame positions -> float32 [n_obj, n, 4] records;
+        grad=True: also the gradient records [n_obj, n, 4] {d phi / d q, 0}."""
         import torch
         assert points.is_cuda and points.dtype == torch.float32 and points.is_contiguous()
         n = points.shape[1]
         if samples is None:
             samples = torch.empty((self.n_obj, n, 4), dtype=torch.float32, device=points.device)
-        self._chk(self.lib.tg_nsdf_targets(self.h, points.data_ptr(), n, samples.data_ptr(), _stream_ptr(stream)),
-                  "tg_nsdf_targets")
-        return samples
+        gs = torch.empty((self.n_obj, n, 4), dtype=torch.float32, device=points.device) if grad else None
+        self._chk(self.lib.tg_nsdf_targets(self.h, points.data_ptr(), n, samples.data_ptr(),
+                                           gs.data_ptr() if grad else None, _stream_ptr(stream)), "tg_nsdf_targets")
+        return (samples, gs) if grad else samples
 
-    def grad(self, params, samples, pair_lambda=0.0, stream=None):
+    def grad(self, params, samples, pair_lambda=0.0, stream=None, grad_samples=None, grad_lambda=0.0):
         import torch
         n = samples.shape[1]
         g = torch.empty_like(params)
         loss = torch.empty(self.n_obj, dtype=torch.float32, device=params.device)
-        self._chk(self.lib.tg_nsdf_grad(self.h, params.data_ptr(), samples.data_ptr(), n, float(pair_lambda),
-                                        g.data_ptr(), loss.data_ptr(), _stream_ptr(stream)), "tg_nsdf_grad")
+        gp = grad_samples.data_ptr() if grad_samples is not None else None
+        self._chk(self.lib.tg_nsdf_grad(self.h, params.data_ptr(), samples.data_ptr(), gp, n, float(pair_lambda),
+                                        float(grad_lambda), g.data_ptr(), loss.data_ptr(), _stream_ptr(stream)),
+                  "tg_nsdf_grad")
         return loss, g
 
     def adam(self, params, m, v, grad, t, hp: TgNsdfTrainParams, stream=None):
         self._chk(self.lib.tg_nsdf_adam(params.data_ptr(), m.data_ptr(), v.data_ptr(), grad.data_ptr(),
                                         params.numel(), int(t), C.byref(hp), _stream_ptr(stream)), "tg_nsdf_adam")
 
-    def train(self, params, m, v, samples, step0, n_steps, hp: TgNsdfTrainParams, loss=None, stream=None):
+    def train(self, params, m, v, samples, step0, n_steps, hp: TgNsdfTrainParams, loss=None, stream=None,
+              grad_samples=None):
         n = samples.shape[1]
         lp = loss.data_ptr() if loss is not None else None
+        gp = grad_samples.data_ptr() if grad_samples is not None else None
         self._chk(self.lib.tg_nsdf_train(self.h, params.data_ptr(), m.data_ptr(), v.data_ptr(), samples.data_ptr(),
-                                         n, int(step0), int(n_steps), C.byref(hp), lp, _stream_ptr(stream)),
+                                         gp, n, int(step0), int(n_steps), C.byref(hp), lp, _stream_ptr(stream)),
                   "tg_nsdf_train")
 
     def query(self, params, offsets, xhat, grad=True, stream=None, noalloc=False, out=None, grad_out=None):
@@ -487,10 +499,122 @@ class Nsdf:
                      xhat.data_ptr(), out.data_ptr(), g.data_ptr() if grad else None, _stream_ptr(stream)), name)
         return (out, g) if grad else out
 
+    def query_trace(self, params, offsets, xhat, stream=None):
+        """tg_nsdf_query_trace: (out [n], grad [n, 3], trace int16 [n, 5, 64] of BF16 bit patterns:
+        row 0 the encoding features, rows 1..4 the hidden layers' pre-activations)."""
+        import torch
+        offs = np.asarray(offsets, np.int64)
+        d_off = torch.from_numpy(offs).to(xhat.device)
+        n = xhat.shape[0]
+        out = torch.empty(n, dtype=torch.float32, device=xhat.device)
+        g = torch.empty((n, 3), dtype=torch.float32, device=xhat.device)
+        tr = torch.zeros((n, 5, 64), dtype=torch.int16, device=xhat.device)
+        self._keep = d_off
+        self._chk(self.lib.tg_nsdf_query_trace(self.h, params.data_ptr(), d_off.data_ptr(),
+                                               int(np.diff(offs).max()) if offs.size > 1 else 0, xhat.data_ptr(),
+                                               out.data_ptr(), g.data_ptr(), tr.data_ptr(), _stream_ptr(stream)),
+                  "tg_nsdf_query_trace")
+        return out, g, tr
+
     def close(self):
         if getattr(self, "h", None):
             self.lib.tg_nsdf_destroy(self.h)
             self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------------------------------------
+# ProximityTaxel readout (include/tg_proximity.h)
+# ------------------------------------------------------------------------------------------------
+class TgPointCloud(C.Structure):
+    _fields_ = [("num_points", C.c_int32), ("points", C.c_void_p)]
+
+
+class TgProxConfig(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("num_envs", C.c_int32), ("num_links", C.c_int32),
+                ("num_taxels", C.c_int32), ("num_objects", C.c_int32), ("link_taxel_offset", C.c_void_p),
+                ("taxel_pos", C.c_void_p), ("taxel_normal", C.c_void_p), ("sensing_radius", C.c_void_p),
+                ("clouds", C.c_void_p), ("k", C.c_float), ("k_s", C.c_float), ("density", C.c_float),
+                ("seed", C.c_uint64), ("radius_rho", C.c_float)]
+
+
+_prox_ready = False
+
+
+def _prox_lib() -> C.CDLL:
+    global _prox_ready
+    lib = load()
+    if not _prox_ready:
+        P = C.c_void_p
+        sig = {"tg_prox_create": ([P, P], C.c_int), "tg_prox_destroy": ([P], C.c_int),
+               "tg_prox_last_error": ([P], C.c_char_p),
+               "tg_prox_rollout": ([P, P, P, P, P, C.c_int32, P], C.c_int)}
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _prox_ready = True
+    return lib
+
+
+class Proximity:
+    """ProximityTaxel readout of a scene's hand over per-object surface point clouds (list of
+    float32 [n][3], object frame).  Inputs and outputs are torch tensors on the current device; this
+    class only passes their pointers to the library."""
+
+    def __init__(self, scene, clouds, radius=0.01, k=300.0, k_s=10.0, density=100.0, seed=0, radius_rho=0.0):
+        import torch
+        self._torch = torch
+        self.lib = _prox_lib()
+        lay = scene.layout
+        self.E, self.T, self.L = scene.num_envs, lay.num_taxels, lay.num_links
+        keep = [np.ascontiguousarray(lay.link_offset, np.int32), np.ascontiguousarray(lay.pos, np.float32),
+                np.ascontiguousarray(lay.normal, np.float32), np.full(self.T, radius, np.float32)]
+        pcs = (TgPointCloud * len(clouds))()
+        for i, c in enumerate(clouds):
+            a = np.ascontiguousarray(c, np.float32).reshape(-1, 3)
+            keep.append(a)
+            pcs[i].num_points = a.shape[0]
+            pcs[i].points = a.ctypes.data
+        cfg = TgProxConfig(ABI_VERSION, self.E, self.L, self.T, len(clouds), keep[0].ctypes.data, keep[1].ctypes.data,
+                           keep[2].ctypes.data, keep[3].ctypes.data, C.cast(pcs, C.c_void_p).value, float(k),
+                           float(k_s), float(density), int(seed), float(radius_rho))
+        h = C.c_void_p()
+        rc = self.lib.tg_prox_create(C.byref(cfg), C.byref(h))
+        if rc != 0:
+            raise TgError(f"tg_prox_create: {self.lib.tg_prox_last_error(None).decode()}")
+        self.h = h
+
+    def rollout(self, dinp: DeviceInputs, n_steps: Optional[int] = None, s_in: int = 0, ft=None, mass=None,
+                gain=None, want_mass: bool = True, stream=None):
+        """Steps s_in .. s_in+n-1 of the device inputs, one launch.  Returns (ft [n][6][E][T],
+        mass [n][E][T] or None)."""
+        torch = self._torch
+        S = dinp.link_state.shape[0] - s_in if n_steps is None else n_steps
+        dev = dinp.link_state.device
+        if ft is None:
+            ft = torch.empty((S, 6, self.E, self.T), dtype=torch.float32, device=dev)
+        if mass is None and want_mass:
+            mass = torch.empty((S, self.E, self.T), dtype=torch.float32, device=dev)
+        ist = TgStepInputs(dinp.link_state[s_in].data_ptr(),
+                           None if dinp.obj_state is None else dinp.obj_state[s_in].data_ptr(),
+                           dinp.obj_id[s_in].data_ptr(), dinp.step0 + s_in)
+        rc = self.lib.tg_prox_rollout(self.h, C.byref(ist), ft.data_ptr(), None if mass is None else mass.data_ptr(),
+                                      None if gain is None else gain.data_ptr(), int(S), _stream_ptr(stream))
+        if rc != 0:
+            raise TgError(f"tg_prox_rollout: {self.lib.tg_status_string(rc).decode()}: "
+                          f"{self.lib.tg_prox_last_error(self.h).decode()}")
+        return ft, mass
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.tg_prox_destroy(self.h)
+            self.h = C.c_void_p()
 
     def __del__(self):
         try:

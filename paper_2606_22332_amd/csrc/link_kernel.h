@@ -78,10 +78,12 @@ __device__ __forceinline__ float group8_sum(float v) {
 }
 
 // The 10 summed channels of one step (f, tau, contact, d * n_z, d * n_y, d * n_x), reduced over
-// each 8-lane group and parked as P[ch][group] by the group's first lane.  An env's lanes are a
-// whole number of groups (n_l padded to a multiple of 8), so every group belongs to one env;
-// lanes outside a readout pass zeros.
-__device__ __forceinline__ void put_group_sums(float* P, int ngroups, const float* v) {
+// each 8-lane group and parked as P[ch][group] by the group's first lane, channel rows `stride`
+// = groups + 1 floats apart: the reduction's lanes (channel, env) then read 10 different banks
+// where a stride of 64 put every channel of an env on one bank.  An env's lanes are a whole
+// number of groups (n_l padded to a multiple of 8), so every group belongs to one env; lanes
+// outside a readout pass zeros.
+__device__ __forceinline__ void put_group_sums(float* P, int stride, const float* v) {
   const bool lead = (threadIdx.x & 7) == 0;
   const int g = threadIdx.x >> 3;
   // the three DPP stages run across all ten channels in turn, so no stage reads a value written
@@ -95,7 +97,7 @@ __device__ __forceinline__ void put_group_sums(float* P, int ngroups, const floa
   for (int c = 0; c < 10; ++c) t[c] = t[c] + dpp_f<0x104>(t[c]);
   if (lead) {
 #pragma unroll
-    for (int c = 0; c < 10; ++c) P[c * ngroups + g] = t[c];
+    for (int c = 0; c < 10; ++c) P[c * stride + g] = t[c];
   }
 }
 
@@ -114,7 +116,7 @@ __device__ __forceinline__ uint32_t lane_roles(int tid, int envs, int nwin) {
 // agg_force) from the group partials: one lane per (channel, env) item adds the env's groups in
 // order; output [11][L][E], items env-fastest so neighbouring lanes store neighbouring floats.
 template <class KP, class LI>
-__device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* P, int ngroups, int e0, int l,
+__device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* P, int stride, int e0, int l,
                                             float* out, uint32_t roles) {
   const int gpe = li.np >> 3;
   const int64_t EL = (int64_t)p.E * p.L;
@@ -123,7 +125,7 @@ __device__ __forceinline__ void link_reduce(KP& p, LI& li, const float* P, int n
     if (ch >= 10) return;
     const int e = e0 + el;
     if (e >= p.E) return;
-    const float* v = P + ch * ngroups + el * gpe;
+    const float* v = P + ch * stride + el * gpe;
     float acc = 0.f;
     for (int g = 0; g < gpe; ++g) acc += v[g];
     // byte offsets from the step's base: 11 * E * L * 4 fits 32 bits (checked at create)
@@ -342,11 +344,11 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
       if (bit) atomicOr(&bw[el * li.nwin * 2 + (wbit >> 5)], 1u << (wbit & 31));
     }
     const bool sums = q.link_sums != nullptr;
-    const int ngroups = nthr >> 3;
+    const int sstride = (nthr >> 3) + 1;   // channel stride of the group partials
     if (sums) {   // (o and tb are zero outside a readout)
       const float v[10] = {o.f[0], o.f[1], o.f[2], o.tau[0], o.tau[1], o.tau[2], bit ? 1.f : 0.f,
                            o.depth * tb.z, o.depth * tb.y, o.depth * tb.x};
-      put_group_sums(S, ngroups, v);
+      put_group_sums(S, sstride, v);
     }
     float z[6] = {gain * o.f[0], gain * o.f[1], gain * o.f[2], gain * o.tau[0], gain * o.tau[1], gain * o.tau[2]};
     if (NOISE && XT == 1) {
@@ -367,7 +369,7 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
     __syncthreads();   // B2: clean bits, sums, crosstalk operands
     TG_REFRESH_PHASE();
     if (q.bits) store_bits(p, li, bw, e0, q.bits + (int64_t)s * p.E * p.W, roles);
-    if (sums) link_reduce(p, li, S, ngroups, e0, l, q.link_sums + (int64_t)s * 11 * EL, roles);
+    if (sums) link_reduce(p, li, S, sstride, e0, l, q.link_sums + (int64_t)s * 11 * EL, roles);
 
     if (NOISE) {
       if (XT >= 2) {
@@ -526,13 +528,13 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
         const float v[10] = {act ? fo[0] : 0.f, act ? fo[1] : 0.f, act ? fo[2] : 0.f,
                              act ? fo[3] : 0.f, act ? fo[4] : 0.f, act ? fo[5] : 0.f,
                              act && nb ? 1.f : 0.f, dd * tn.z, dd * tn.y, dd * tn.x};
-        put_group_sums(S, ngroups, v);
+        put_group_sums(S, sstride, v);
       }
       if (pre && pf_off != -1) RAW[(par ^ 1) * nraw + tid] = rv;   // park the next step's inputs
       __syncthreads();   // B4: noisy bits and sums
       TG_REFRESH_PHASE();
       if (q.bits_noisy) store_bits(p, li, bwn, e0, q.bits_noisy + (int64_t)s * p.E * p.W, roles);
-      if (sums_n) link_reduce(p, li, S, ngroups, e0, l, q.link_sums_noisy + (int64_t)s * 11 * EL, roles);
+      if (sums_n) link_reduce(p, li, S, sstride, e0, l, q.link_sums_noisy + (int64_t)s * 11 * EL, roles);
     }
   }
   TG_REFRESH();

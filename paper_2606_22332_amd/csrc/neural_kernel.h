@@ -188,6 +188,8 @@ __global__ __launch_bounds__(NEU_THREADS, 2) void tg_neural_kernel(const NLaunch
           const int src = 16 * tt + s;
           const float x0 = __shfl(xh[0], src), x1 = __shfl(xh[1], src), x2 = __shfl(xh[2], src);
           const float rj = __shfl(rnet, src);
+          // a tile whose 16 taxels are all outside the box (or fillers) needs no network value
+          if (!__any(rj > -INFINITY)) continue;
           uint32_t z[4][8];
           u32x4 pe[2];
           float a4[4][4];

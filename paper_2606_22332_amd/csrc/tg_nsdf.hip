@@ -64,8 +64,37 @@ __device__ __forceinline__ float grid_value(const GridDesc& gd, const float* __r
   return lerpf(t[2], y0, y1);
 }
 
+// Analytic gradient of the same trilinear interpolant (App. A.1: the normal is the SDF gradient):
+// the corner differences along each axis, interpolated over the other two, times 1/h.
+__device__ __forceinline__ void grid_gradient(const GridDesc& gd, const float* __restrict__ vals, const float* q,
+                                              float gr[3]) {
+  float t[3];
+  int i[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float u = (q[d] - gd.origin[d]) * gd.hinv;
+    const float uc = fminf(fmaxf(u, 0.0f), gd.nm1);
+    const int ii = min((int)floorf(uc), gd.n - 2);
+    i[d] = ii;
+    t[d] = uc - (float)ii;
+  }
+  const int n = gd.n;
+  const float* c = vals + gd.offset + ((int64_t)i[2] * n + i[1]) * n + i[0];
+  const int sy = n, sz = n * n;
+  const float c000 = c[0], c100 = c[1], c010 = c[sy], c110 = c[sy + 1];
+  const float c001 = c[sz], c101 = c[sz + 1], c011 = c[sz + sy], c111 = c[sz + sy + 1];
+  const float x00 = lerpf(t[0], c000, c100), x10 = lerpf(t[0], c010, c110);
+  const float x01 = lerpf(t[0], c001, c101), x11 = lerpf(t[0], c011, c111);
+  const float y0 = lerpf(t[1], x00, x10), y1 = lerpf(t[1], x01, x11);
+  const float dx0 = lerpf(t[1], c100 - c000, c110 - c010), dx1 = lerpf(t[1], c101 - c001, c111 - c011);
+  gr[0] = lerpf(t[2], dx0, dx1) * gd.hinv;
+  gr[1] = lerpf(t[2], x10 - x00, x11 - x01) * gd.hinv;
+  gr[2] = (y1 - y0) * gd.hinv;
+}
+
 __global__ void nsdf_targets_kernel(const BoxDesc* __restrict__ boxes, const float* __restrict__ vals,
-                                    const float* __restrict__ pts, int64_t n, float4* __restrict__ out) {
+                                    const float* __restrict__ pts, int64_t n, float4* __restrict__ out,
+                                    float4* __restrict__ gout) {
   const int o = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -77,6 +106,11 @@ __global__ void nsdf_targets_kernel(const BoxDesc* __restrict__ boxes, const flo
   const float phi = grid_value(b.grid, vals, q);
   out[k] = make_float4((q[0] - b.centre[0]) * b.half_inv, (q[1] - b.centre[1]) * b.half_inv,
                        (q[2] - b.centre[2]) * b.half_inv, phi * b.half_inv);
+  if (gout) {   // d phi / d q, which is also d(phi / e) / d x_hat
+    float gr[3];
+    grid_gradient(b.grid, vals, q, gr);
+    gout[k] = make_float4(gr[0], gr[1], gr[2], 0.0f);
+  }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -96,7 +130,10 @@ constexpr int STAGE_U16 = 64 * SROW;        // one [64 feature][16 sample] buffe
 constexpr int STAGE_BYTES = 4 * 4 * 2 * STAGE_U16 * 2;   // [wave][layer][dz | act]
 constexpr int RED_FLOATS = 4 * 66 + 4;      // per wave: dw5[64], db5, loss; then the summed loss
 static_assert(B5_OFF == W5_OFF + 64, "db5 follows dw5 in the parameter vector");
-constexpr int LDS_FIT = IMG_BYTES + STAGE_BYTES + RED_FLOATS * 4;   // dynamic; the SiLU table is static
+static_assert(STAGE_BYTES >= NPARAM * 4, "the step's gradient reuses the staging area");
+// dynamic; with the static SiLU table (13,312 B) the kernel takes 161,328 B of the CU's 160 KiB
+constexpr int LDS_FIT = IMG_BYTES + STAGE_BYTES + RED_FLOATS * 4;
+static_assert(LDS_FIT + SILU_BYTES <= 160 * 1024, "fits one CU's LDS");
 
 __device__ __forceinline__ uint16_t* stage_buf(uint8_t* smem, int wave, int l, int which) {
   return (uint16_t*)(smem + IMG_BYTES) + ((wave * 4 + l) * 2 + which) * STAGE_U16;
@@ -189,8 +226,217 @@ __device__ __forceinline__ void tile_backprop(const Img& im, uint8_t* smem, int 
   }
 }
 
+// The same for a loss with the gradient term grad_lambda * sum_d |g_d - gt_d| (g = d out / d x_hat,
+// gt the grid's gradient, grec.xyz).  With u = grad_lambda sign(g - gt) / n held fixed, the term's
+// parameter gradient is that of u . g, the directional derivative of out along u, which a
+// forward-mode tangent pass computes: adot_0 = J_enc u, zdot_l = W_l adot_l, adot_l+1 = silu'(z_l)
+// zdot_l, u . g = w5 . adot_4.  Reverse mode through both chains gives per layer
+//   zdbar = adbar silu'(z),  zbar = abar silu'(z) + adbar silu''(z) zdot,
+//   dW_l += zbar a_l^T + zdbar adot_l^T,  db_l += zbar,  dw5 += go a_4 + adot_4,
+// where adbar is the adjoint of the plain input-gradient pass (seed w5).  BF16 rounding as in the
+// MFMA forward: the GEMM operands (adot_0..3, zdot, zbar, zdbar and the weights) are BF16, adot_4 and
+// every sum FP32.  The LDS holds two staged operands per (wave, layer), so a round contracts twice:
+// gs_first stages (zdbar, adot) and gs_second (zbar, a).  gs_second runs the input-gradient pass
+// again beside the zbar chain (the same MFMA operands give the same adbar, bit for bit) instead of
+// keeping its 48 FP32 values per lane alive across the first contraction.
+__device__ __forceinline__ void gs_first(const Img& im, uint8_t* smem, int wave, int lane, float4 rec, float4 grec,
+                                         bool valid, float inv_n, float pair_lambda, float grad_lambda,
+                                         float dw5[4][4], float& db5, float& loss, const uint16_t* tab,
+                                         uint32_t z[4][8], u32x4 pe[2], uint32_t zd[4][8], float& go) {
+  const int g = lane >> 4, s = lane & 15;
+  float a4[4][4];
+  const float out = forward_tile(im, lane, rec.x, rec.y, rec.z, z, pe, a4, tab);
+  const float r = out - rec.w;
+  go = valid ? ((r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f)) * inv_n) : 0.f;
+  float lp = fabsf(r);
+  if (pair_lambda > 0.f) {   // uniform
+    const float dr = r - __shfl_xor(r, 1);
+    if (valid) go += pair_lambda * ((dr > 0.f ? 1.f : (dr < 0.f ? -1.f : 0.f)) * inv_n);
+    if ((s & 1) == 0) lp += pair_lambda * fabsf(dr);
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dw5[m][q] = fmaf(go, a4[m][q], dw5[m][q]);
+  // input-gradient pass (seed w5); its dz are zdbar, staged as the first operand
+  float ad[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) ad[m][q] = im.tail[256 + 16 * m + 4 * g + q];
+  f32x4 gf[3];
+#pragma unroll
+  for (int l = 3; l >= 0; --l) {
+    __builtin_amdgcn_sched_barrier(0);
+    u32x4 db[2];
+    float dz[4][4];
+    dz_frags(ad, z[l], db, dz);
+    stage_frags(stage_buf(smem, wave, l, 0), db, g, s, false);
+    if (l > 0) {
+      f32x4 o[4];
+      layer_bwd<4>(im, l, lane, db, o);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ad[m][q] = o[m][q];
+    } else {
+      layer_bwd<3>(im, 0, lane, db, gf);
+    }
+  }
+  const float xs[3] = {rec.x, rec.y, rec.z};
+  float gp[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {   // feature f = 16m + 4g + q = 6k + 3c + d (c = 0 sine, 1 cosine)
+      const int f = 16 * m + 4 * g + q;
+      const int k = f / 6, rem = f - 6 * k, c = rem / 3, d = rem - 3 * c;
+      const float t = __builtin_amdgcn_fractf((float)(1 << k) * 0.5f * xs[d]);
+      const float w = (float)(1 << k) * 3.14159265358979323846f;
+      const float dv = c == 0 ? w * __builtin_amdgcn_cosf(t) : -w * __builtin_amdgcn_sinf(t);
+      const float contrib = gf[m][q] * dv;
+      gp[0] += d == 0 ? contrib : 0.f;
+      gp[1] += d == 1 ? contrib : 0.f;
+      gp[2] += d == 2 ? contrib : 0.f;
+    }
+  const float gt[3] = {grec.x, grec.y, grec.z};
+  float u[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float e = group_sum(gp[d]) - gt[d];
+    lp += grad_lambda * fabsf(e);
+    u[d] = valid ? grad_lambda * ((e > 0.f ? 1.f : (e < 0.f ? -1.f : 0.f)) * inv_n) : 0.f;
+  }
+  if (g == 0 && valid) {
+    loss += lp;
+    db5 += go;
+  }
+  // tangent pass along u: adot_l (BF16) staged as the second operand, zdot_l (BF16) kept
+  u32x4 bin[2];
+#pragma unroll
+  for (int kt = 0; kt < 2; ++kt) {   // encoding order: lane group g of K-tile kt is frequency 4kt + g
+    const int k = 4 * kt + g;
+    const float sc = (float)(1 << k) * 0.5f, w = (float)(1 << k) * 3.14159265358979323846f;
+    float v[6];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float t = __builtin_amdgcn_fractf(sc * xs[d]);
+      v[d] = (w * __builtin_amdgcn_cosf(t)) * u[d];
+      v[3 + d] = (-w * __builtin_amdgcn_sinf(t)) * u[d];
+    }
+    bin[kt] = u32x4{pack2(v[0], v[1]), pack2(v[2], v[3]), pack2(v[4], v[5]), 0u};
+  }
+#pragma unroll
+  for (int l = 0; l < 4; ++l) {
+    __builtin_amdgcn_sched_barrier(0);
+    stage_frags(stage_buf(smem, wave, l, 1), bin, g, s, l == 0);
+    f32x4 acc[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt) acc[m] = mfma32(frag(im.fwd, (l * 4 + m) * 2 + kt, lane), bin[kt], acc[m]);
+    }
+    float av[4][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      zd[l][2 * m] = pack2(acc[m][0], acc[m][1]);
+      zd[l][2 * m + 1] = pack2(acc[m][2], acc[m][3]);
+      const float zz[4] = {bf_lo(z[l][2 * m]), bf_hi(z[l][2 * m]), bf_lo(z[l][2 * m + 1]), bf_hi(z[l][2 * m + 1])};
+      const float dd[4] = {bf_lo(zd[l][2 * m]), bf_hi(zd[l][2 * m]), bf_lo(zd[l][2 * m + 1]),
+                           bf_hi(zd[l][2 * m + 1])};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float sg = sigmoid(zz[q]);
+        av[m][q] = (sg * fmaf(zz[q], 1.0f - sg, 1.0f)) * dd[q];
+      }
+    }
+    if (l < 3) {
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt)
+        bin[kt] = u32x4{pack2(av[2 * kt][0], av[2 * kt][1]), pack2(av[2 * kt][2], av[2 * kt][3]),
+                        pack2(av[2 * kt + 1][0], av[2 * kt + 1][1]), pack2(av[2 * kt + 1][2], av[2 * kt + 1][3])};
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dw5[m][q] = dw5[m][q] + av[m][q];
+    }
+  }
+}
+
+__device__ __forceinline__ void gs_second(const Img& im, uint8_t* smem, int wave, int lane, const uint32_t z[4][8],
+                                          const u32x4 pe[2], const uint32_t zd[4][8], float go,
+                                          const uint16_t* tab) {
+  const int g = lane >> 4, s = lane & 15;
+  float ab[4][4], ad[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      ad[m][q] = im.tail[256 + 16 * m + 4 * g + q];
+      ab[m][q] = go * ad[m][q];
+    }
+#pragma unroll
+  for (int l = 3; l >= 0; --l) {
+    __builtin_amdgcn_sched_barrier(0);
+    // zbar (needs adbar) first; then zdbar, the next adbar and the next abar
+    u32x4 db[2], dbd[2], ain[2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+      uint32_t w[4], wd[4];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int m = 2 * kt + h;
+        const float zz[4] = {bf_lo(z[l][2 * m]), bf_hi(z[l][2 * m]), bf_lo(z[l][2 * m + 1]), bf_hi(z[l][2 * m + 1])};
+        const float dd[4] = {bf_lo(zd[l][2 * m]), bf_hi(zd[l][2 * m]), bf_lo(zd[l][2 * m + 1]),
+                             bf_hi(zd[l][2 * m + 1])};
+        float zb[4], zdb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float sg = sigmoid(zz[q]);
+          const float d1 = sg * fmaf(zz[q], 1.0f - sg, 1.0f);
+          const float d2 = (sg * (1.0f - sg)) * fmaf(zz[q], 1.0f - 2.0f * sg, 2.0f);
+          zdb[q] = ad[m][q] * d1;
+          zb[q] = ab[m][q] * d1 + (ad[m][q] * d2) * dd[q];
+        }
+        w[2 * h] = pack2(zb[0], zb[1]);
+        w[2 * h + 1] = pack2(zb[2], zb[3]);
+        wd[2 * h] = pack2(zdb[0], zdb[1]);
+        wd[2 * h + 1] = pack2(zdb[2], zdb[3]);
+      }
+      db[kt] = u32x4{w[0], w[1], w[2], w[3]};
+      dbd[kt] = u32x4{wd[0], wd[1], wd[2], wd[3]};
+    }
+    stage_frags(stage_buf(smem, wave, l, 0), db, g, s, false);
+    if (l == 0) {
+      ain[0] = pe[0];
+      ain[1] = pe[1];
+    } else {
+      act_frags_tab(z[l - 1], ain, tab);
+    }
+    stage_frags(stage_buf(smem, wave, l, 1), ain, g, s, l == 0);
+    if (l > 0) {
+      f32x4 o[4];
+      layer_bwd<4>(im, l, lane, dbd, o);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ad[m][q] = o[m][q];
+      layer_bwd<4>(im, l, lane, db, o);
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ab[m][q] = o[m][q];
+    }
+  }
+}
+
 // Weight and bias gradient of layer L over the four staged tiles (owner wave only).
-__device__ __forceinline__ void owner_wgrad(uint8_t* smem, int L, int lane, f32x4 acc[4][4], float dbp[4]) {
+// bias = false: a second pass over other staged operands (the gradient term's zdbar against
+// adot), which adds to the weight gradient only.
+__device__ __forceinline__ void owner_wgrad(uint8_t* smem, int L, int lane, f32x4 acc[4][4], float dbp[4],
+                                            bool bias) {
   const int g = lane >> 4, s = lane & 15;
   const int nin = L == 0 ? 3 : 4;
 #pragma unroll
@@ -203,7 +449,7 @@ __device__ __forceinline__ void owner_wgrad(uint8_t* smem, int L, int lane, f32x
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       A[m] = stage_pair(d0, d1, 16 * m + s, g);
-      dbp[m] += bf_sum8(A[m]);
+      if (bias) dbp[m] += bf_sum8(A[m]);
     }
 #pragma unroll
     for (int n = 0; n < 4; ++n)
@@ -236,12 +482,14 @@ struct FitArgs {
   float lr, b1, b2, eps;
   uint32_t key0, key1;
   float pair_lambda;        // > 0: records (2i, 2i+1) are pairs, loss adds lambda |r_odd - r_even|
+  const float4* gsamples;   // [n_obj][n] grid gradients {d phi / d q, 0} (gradient term only)
+  float grad_lambda;        // > 0: loss adds grad_lambda sum_d |g_d - gt_d| per record
   const uint16_t* silu;     // SiLU table (global copy; staged in LDS)
 };
 
 }  // namespace
 
-template <int TRAIN>
+template <int TRAIN, int GS>
 __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int o = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, s = lane & 15;
@@ -250,6 +498,7 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
   float* red = (float*)(smem + IMG_BYTES + STAGE_BYTES);
   float* Po = a.P + (size_t)o * NPARAM;
   const float4* So = a.samples + (size_t)o * a.n;
+  const float4* Go = GS ? a.gsamples + (size_t)o * a.n : nullptr;
   for (int w = tid; w < IMG_WORDS; w += NT) ((uint32_t*)smem)[w] = image_word(Po, w);
   __shared__ __align__(16) uint16_t tab[SILU_ENTRIES];
   for (int i = tid; i < SILU_ENTRIES / 2; i += NT) ((uint32_t*)tab)[i] = ((const uint32_t*)a.silu)[i];
@@ -290,9 +539,24 @@ __global__ __launch_bounds__(NT, 1) void nsdf_fit_kernel(const FitArgs a) {
         valid = j < a.n;
       }
       const float4 rec = valid ? So[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-      tile_backprop(im, smem, wave, lane, rec, valid, inv_n, a.pair_lambda, dw5, db5, lossp, tab);
-      __syncthreads();
-      owner_wgrad(smem, L, lane, acc, dbp);
+      if (GS) {
+        const float4 grec = valid ? Go[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+        uint32_t z[4][8], zd[4][8];
+        u32x4 pe[2];
+        float go;
+        gs_first(im, smem, wave, lane, rec, grec, valid, inv_n, a.pair_lambda, a.grad_lambda, dw5, db5, lossp, tab,
+                 z, pe, zd, go);
+        __syncthreads();
+        owner_wgrad(smem, L, lane, acc, dbp, false);   // zdbar against adot
+        __syncthreads();
+        gs_second(im, smem, wave, lane, z, pe, zd, go, tab);
+        __syncthreads();
+        owner_wgrad(smem, L, lane, acc, dbp, true);    // zbar against a
+      } else {
+        tile_backprop(im, smem, wave, lane, rec, valid, inv_n, a.pair_lambda, dw5, db5, lossp, tab);
+        __syncthreads();
+        owner_wgrad(smem, L, lane, acc, dbp, true);
+      }
       __syncthreads();
     }
     // Gradient of the step into LDS (the staging area is free now): owners write their layer,
@@ -406,10 +670,13 @@ __global__ void nsdf_adam_kernel(float* __restrict__ P, float* __restrict__ M, f
 
 // Evaluation: one workgroup per (object, chunk of 64*k points), image of that object in LDS.
 constexpr int QUERY_TILES_PER_WAVE = 8;
+// trace (or null): per point [5][64] BF16 bits, row 0 the 48 encoding features (feature order of
+// the encoding), rows 1..4 the BF16 pre-activations of the four hidden layers (unit order).
 __global__ __launch_bounds__(NT) void nsdf_query_kernel(const uint32_t* __restrict__ images,
                                                         const int64_t* __restrict__ offsets,
                                                         const float* __restrict__ xhat, float* __restrict__ out,
-                                                        float* __restrict__ grad, const uint16_t* __restrict__ silu) {
+                                                        float* __restrict__ grad, const uint16_t* __restrict__ silu,
+                                                        uint16_t* __restrict__ trace) {
   extern __shared__ __align__(16) uint8_t smem[];
   const int o = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t beg = offsets[o], end = offsets[o + 1];
@@ -438,6 +705,26 @@ __global__ __launch_bounds__(NT) void nsdf_query_kernel(const uint32_t* __restri
     const float y = forward_tile(im, lane, x0, x1, x2, z, pe, a4, tab);
     float gx[3] = {0.f, 0.f, 0.f};
     if (grad) input_grad_tile(im, lane, x0, x1, x2, z, gx);
+    if (trace && valid) {
+      const int g = lane >> 4;
+      uint16_t* tr = trace + i * 320;
+#pragma unroll
+      for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+        for (int it = 0; it < 6; ++it) {
+          const uint32_t w = pe[kt][it >> 1];
+          tr[6 * (4 * kt + g) + it] = (uint16_t)((it & 1) ? (w >> 16) : (w & 0xffffu));
+        }
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const uint32_t w = z[l][2 * m + (r >> 1)];
+            tr[64 * (l + 1) + 16 * m + 4 * g + r] = (uint16_t)((r & 1) ? (w >> 16) : (w & 0xffffu));
+          }
+    }
     if (valid && lane < 16) {
       out[i] = y;
       if (grad) {
@@ -479,13 +766,15 @@ hipError_t nsdf_pack_images(const float* params, int n_obj, uint32_t* images, hi
 // Pack the parameters into per-object images at img, then evaluate the points (both launches on
 // the caller's stream).  Shared by the handle's own image buffer and the static one below.
 static tg_status launch_query(tg_nsdf* h, uint32_t* img, const float* params, const int64_t* offsets,
-                              int64_t max_count, const float* xhat, float* out, float* grad, hipStream_t s) {
+                              int64_t max_count, const float* xhat, float* out, float* grad, hipStream_t s,
+                              uint16_t* trace = nullptr) {
   hipLaunchKernelGGL(nsdf_pack_kernel, dim3((IMG_WORDS + 255) / 256, h->n_obj), dim3(256), 0, s, params, h->n_obj,
                      img);
   if (max_count > 0) {
     const int64_t per_block = 4 * 16 * QUERY_TILES_PER_WAVE;
     const dim3 grid((unsigned)((max_count + per_block - 1) / per_block), (unsigned)h->n_obj);
-    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES, s, img, offsets, xhat, out, grad, h->d_silu);
+    hipLaunchKernelGGL(nsdf_query_kernel, grid, dim3(NT), IMG_BYTES, s, img, offsets, xhat, out, grad, h->d_silu,
+                       trace);
   }
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
@@ -517,6 +806,29 @@ tg_status scratch_addr(tg_nsdf* h, int dev, uint32_t** out) {
   }
   *out = g_scratch_addr[dev];
   return TG_OK;
+}
+}  // namespace
+
+namespace {
+// Checks shared by the gradient and training entry points; nullptr when the arguments are valid.
+const char* loss_terms_error(int64_t n, float pair_lambda, float grad_lambda, const float* samples,
+                             const float* grad_samples) {
+  if (!(pair_lambda >= 0.f) || (pair_lambda > 0.f && (n & 1)))
+    return "pair_lambda must be >= 0, with an even n when > 0";
+  if (!(grad_lambda >= 0.f) || (grad_lambda > 0.f && !grad_samples))
+    return "grad_lambda must be >= 0, with grad_samples when > 0";
+  if (!aligned16(samples) || (grad_lambda > 0.f && !aligned16(grad_samples))) return "samples not 16-byte aligned";
+  return nullptr;
+}
+
+template <int TRAIN, int GS>
+tg_status launch_fit(tg_nsdf* h, const FitArgs& a, hipStream_t stream) {
+  hipError_t e = hipFuncSetAttribute((const void*)nsdf_fit_kernel<TRAIN, GS>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, LDS_FIT);
+  if (e != hipSuccess) return nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+  hipLaunchKernelGGL((nsdf_fit_kernel<TRAIN, GS>), dim3(h->n_obj), dim3(NT), LDS_FIT, stream, a);
+  e = hipGetLastError();
+  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
 }
 }  // namespace
 
@@ -594,27 +906,26 @@ tg_status tg_nsdf_destroy(tg_nsdf* h) {
 
 const char* tg_nsdf_last_error(const tg_nsdf* h) { return h ? h->err.c_str() : g_nsdf_create_error.c_str(); }
 
-tg_status tg_nsdf_targets(tg_nsdf* h, const float* points, int64_t n, float* samples, void* stream) {
+tg_status tg_nsdf_targets(tg_nsdf* h, const float* points, int64_t n, float* samples, float* grad_samples,
+                          void* stream) {
   if (!h) return TG_ERR_INVALID_ARGUMENT;
   if (!points || !samples || n < 1) return nfail(h, TG_ERR_INVALID_ARGUMENT, "targets: null pointer or n < 1");
-  if (!aligned16(samples)) return nfail(h, TG_ERR_INVALID_ARGUMENT, "targets: samples not 16-byte aligned");
+  if (!aligned16(samples) || (grad_samples && !aligned16(grad_samples)))
+    return nfail(h, TG_ERR_INVALID_ARGUMENT, "targets: samples not 16-byte aligned");
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)h->n_obj);
   hipLaunchKernelGGL(nsdf_targets_kernel, grid, dim3(256), 0, (hipStream_t)stream, h->d_boxes, h->d_vals, points, n,
-                     (float4*)samples);
+                     (float4*)samples, (float4*)grad_samples);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
 }
 
-tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, int64_t n, float pair_lambda,
-                       float* grad, float* loss, void* stream) {
+
+tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, const float* grad_samples, int64_t n,
+                       float pair_lambda, float grad_lambda, float* grad, float* loss, void* stream) {
   if (!h) return TG_ERR_INVALID_ARGUMENT;
   if (!params || !samples || !grad || n < 1) return nfail(h, TG_ERR_INVALID_ARGUMENT, "grad: null pointer or n < 1");
-  if (!(pair_lambda >= 0.f) || (pair_lambda > 0.f && (n & 1)))
-    return nfail(h, TG_ERR_INVALID_ARGUMENT, "grad: pair_lambda must be >= 0, with an even n when > 0");
-  if (!aligned16(samples)) return nfail(h, TG_ERR_INVALID_ARGUMENT, "grad: samples not 16-byte aligned");
-  hipError_t e = hipFuncSetAttribute((const void*)nsdf_fit_kernel<0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     LDS_FIT);
-  if (e != hipSuccess) return nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+  if (const char* m = loss_terms_error(n, pair_lambda, grad_lambda, samples, grad_samples))
+    return nfail(h, TG_ERR_INVALID_ARGUMENT, std::string("grad: ") + m);
   FitArgs a{};
   a.P = const_cast<float*>(params);
   a.samples = (const float4*)samples;
@@ -623,10 +934,10 @@ tg_status tg_nsdf_grad(tg_nsdf* h, const float* params, const float* samples, in
   a.loss = loss;
   a.n_obj = h->n_obj;
   a.pair_lambda = pair_lambda;
+  a.gsamples = (const float4*)grad_samples;
+  a.grad_lambda = grad_lambda;
   a.silu = h->d_silu;
-  hipLaunchKernelGGL(nsdf_fit_kernel<0>, dim3(h->n_obj), dim3(NT), LDS_FIT, (hipStream_t)stream, a);
-  e = hipGetLastError();
-  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+  return grad_lambda > 0.f ? launch_fit<0, 1>(h, a, (hipStream_t)stream) : launch_fit<0, 0>(h, a, (hipStream_t)stream);
 }
 
 tg_status tg_nsdf_adam(float* params, float* m, float* v, const float* grad, int64_t count, int64_t t,
@@ -639,19 +950,16 @@ tg_status tg_nsdf_adam(float* params, float* m, float* v, const float* grad, int
   return hipGetLastError() == hipSuccess ? TG_OK : TG_ERR_HIP;
 }
 
-tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const float* samples, int64_t n,
-                        int64_t step0, int32_t n_steps, const tg_nsdf_train_params* hp, float* loss, void* stream) {
+tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const float* samples, const float* grad_samples,
+                        int64_t n, int64_t step0, int32_t n_steps, const tg_nsdf_train_params* hp, float* loss,
+                        void* stream) {
   if (!h) return TG_ERR_INVALID_ARGUMENT;
   if (!params || !m || !v || !samples || !hp) return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: null pointer");
   if (n < 1 || n > 0xffffffffLL || step0 < 0 || n_steps < 1 || step0 + n_steps > 0xffffffffLL)
     return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: bad n / step range");
   if (hp->batch < 64 || hp->batch % 64) return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: batch must be a multiple of 64");
-  if (!(hp->pair_lambda >= 0.f) || (hp->pair_lambda > 0.f && (n & 1)))
-    return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: pair_lambda must be >= 0, with an even n when > 0");
-  if (!aligned16(samples)) return nfail(h, TG_ERR_INVALID_ARGUMENT, "train: samples not 16-byte aligned");
-  hipError_t e = hipFuncSetAttribute((const void*)nsdf_fit_kernel<1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     LDS_FIT);
-  if (e != hipSuccess) return nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+  if (const char* msg = loss_terms_error(n, hp->pair_lambda, hp->grad_lambda, samples, grad_samples))
+    return nfail(h, TG_ERR_INVALID_ARGUMENT, std::string("train: ") + msg);
   FitArgs a{};
   a.P = params;
   a.M = m;
@@ -670,10 +978,11 @@ tg_status tg_nsdf_train(tg_nsdf* h, float* params, float* m, float* v, const flo
   a.key0 = (uint32_t)hp->seed;
   a.key1 = (uint32_t)(hp->seed >> 32);
   a.pair_lambda = hp->pair_lambda;
+  a.gsamples = (const float4*)grad_samples;
+  a.grad_lambda = hp->grad_lambda;
   a.silu = h->d_silu;
-  hipLaunchKernelGGL(nsdf_fit_kernel<1>, dim3(h->n_obj), dim3(NT), LDS_FIT, (hipStream_t)stream, a);
-  e = hipGetLastError();
-  return e == hipSuccess ? TG_OK : nfail(h, TG_ERR_HIP, hipGetErrorString(e));
+  return hp->grad_lambda > 0.f ? launch_fit<1, 1>(h, a, (hipStream_t)stream)
+                               : launch_fit<1, 0>(h, a, (hipStream_t)stream);
 }
 
 tg_status tg_nsdf_query(tg_nsdf* h, const float* params, const int64_t* offsets, int64_t max_count,
@@ -682,6 +991,15 @@ tg_status tg_nsdf_query(tg_nsdf* h, const float* params, const int64_t* offsets,
   if (!params || !offsets || !out || !xhat) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query: null pointer");
   if (max_count < 0) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query: max_count < 0");
   return launch_query(h, h->d_img, params, offsets, max_count, xhat, out, grad, (hipStream_t)stream);
+}
+
+tg_status tg_nsdf_query_trace(tg_nsdf* h, const float* params, const int64_t* offsets, int64_t max_count,
+                              const float* xhat, float* out, float* grad, uint16_t* trace, void* stream) {
+  if (!h) return TG_ERR_INVALID_ARGUMENT;
+  if (!params || !offsets || !out || !xhat || !trace)
+    return nfail(h, TG_ERR_INVALID_ARGUMENT, "query_trace: null pointer");
+  if (max_count < 0) return nfail(h, TG_ERR_INVALID_ARGUMENT, "query_trace: max_count < 0");
+  return launch_query(h, h->d_img, params, offsets, max_count, xhat, out, grad, (hipStream_t)stream, trace);
 }
 
 tg_status tg_nsdf_query_noalloc(tg_nsdf* h, const float* params, const int64_t* offsets, int64_t max_count,

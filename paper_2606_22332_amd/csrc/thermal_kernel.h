@@ -27,6 +27,14 @@ struct ThermalParams {
   const float* T_obj;          // [E]
   float* fields;               // [E][F][n^3], index ((z * n) + y) * n + x
   float r, g, rho_f, kappa, T_amb, T0;
+  // the paper's step (App. D.1): spectral diffusion, T^4 radiation and convection, sensor lag
+  int32_t spectral;
+  const float* dct;            // [16][16] orthonormal DCT-II, row m: w_m cos(pi m (2i + 1) / 32)
+  const float* hk;             // [3 * 15^2 + 1] h(s) = a k^2 / (1 + a k^2), k^2 = (pi / (n dx))^2 s
+  float k_rad;                 // dt eps sigma / (rho c_p dx) per exposed face
+  float k_conv;                // dt h / (rho c_p dx) per exposed face
+  float lag;                   // dt / tau of the sensor element, 0 = no lag
+  float* t_meas;               // [E][T] measured reading (state), when lag > 0
 };
 
 struct ThermalLaunch {
@@ -41,7 +49,86 @@ struct ThermalLaunch {
                                // kernel before this launch), or null: recomputed here
 };
 
-__global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const ThermalLaunch q) {
+// 16-point transforms with the DCT-II matrix (forward y = C v, inverse y = C^T v).  The matrix and
+// its transpose sit in LDS (Cs, Ct), read row by row with uniform addresses (one broadcast 16-byte
+// read per four coefficients); the input v is in registers.
+__device__ __forceinline__ float dct16_row(const float* Cr, const float v[TH_N]) {
+  const float4* row = (const float4*)Cr;
+  float a = 0.f;
+#pragma unroll
+  for (int q = 0; q < TH_N / 4; ++q) {
+    const float4 c = row[q];
+    a = fmaf(c.x, v[4 * q], a);
+    a = fmaf(c.y, v[4 * q + 1], a);
+    a = fmaf(c.z, v[4 * q + 2], a);
+    a = fmaf(c.w, v[4 * q + 3], a);
+  }
+  return a;
+}
+// All 16 outputs written to LDS at dst[m * stride]: a rolled loop over the outputs keeps only v
+// and one accumulator live.
+__device__ __forceinline__ void dct16_to_lds(const float* Cr, const float v[TH_N], float* dst, int stride) {
+#pragma unroll 1
+  for (int m = 0; m < TH_N; ++m) dst[m * stride] = dct16_row(Cr + m * TH_N, v);
+}
+
+// The paper's spectral diffusion step (App. D.1) on the block held as z-columns `col` (thread (x,y)).
+// The mirror-padded FFT filter 1 / (1 + a k^2) is diagonal in the DCT-II basis of the block, with
+// k^2 = (pi / (n dx))^2 (mx^2 + my^2 + mz^2).  It is applied in the equal correction form
+//   T' = T - C3^T (h * C3 T),   h = a k^2 / (1 + a k^2) <= a k_max^2,
+// so the FP32 rounding of the transforms multiplies only the small correction.  C3 is separable:
+// each axis in turn, the data going through the exchange buffer (rows padded to 17 floats,
+// conflict-free), thread (x, y) for z, (x, mz) for y, (my, mz) for x.
+__device__ __forceinline__ void spectral_diffuse(const float* Cs, const float* Ct, const float* hk, float col[TH_N],
+                                                 float* ex, int tid) {
+  constexpr int n = TH_N, RS = TH_N + 1;   // padded row stride
+  const int x = tid % n, y = tid / n;
+  float v[n];
+  // forward z: thread (x, y) -> ex[mz][y][x]
+  dct16_to_lds(Cs, col, ex + y * RS + x, n * RS);
+  __syncthreads();
+  // forward y: thread (x, mz) reads ex[mz][.][x], writes ex[mz][my][x]
+#pragma unroll
+  for (int i = 0; i < n; ++i) v[i] = ex[(y * n + i) * RS + x];
+  __syncthreads();
+  dct16_to_lds(Cs, v, ex + y * n * RS + x, RS);
+  __syncthreads();
+  // forward x, scale by h, inverse x: thread (my, mz) on row ex[mz][my][.]
+  {
+    const int my = x, mz = y;
+    float* rowp = ex + (mz * n + my) * RS;
+#pragma unroll
+    for (int i = 0; i < n; ++i) v[i] = rowp[i];
+    float w[n];
+#pragma unroll
+    for (int mx = 0; mx < n; ++mx) {
+      w[mx] = dct16_row(Cs + mx * n, v) * hk[mx * mx + my * my + mz * mz];
+      __builtin_amdgcn_sched_barrier(0);   // one row's coefficients live at a time
+    }
+    dct16_to_lds(Ct, w, rowp, 1);
+  }
+  __syncthreads();
+  // inverse y: thread (x, mz)
+#pragma unroll
+  for (int m = 0; m < n; ++m) v[m] = ex[(y * n + m) * RS + x];
+  __syncthreads();
+  dct16_to_lds(Ct, v, ex + y * n * RS + x, RS);
+  __syncthreads();
+  // inverse z: thread (x, y); subtract the correction
+#pragma unroll
+  for (int m = 0; m < n; ++m) v[m] = ex[(m * n + y) * RS + x];
+#pragma unroll
+  for (int z = 0; z < n; ++z) {
+    col[z] = col[z] - dct16_row(Ct + z * n, v);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();   // the exchange buffer is free again
+}
+
+// SPEC = 1: the paper's step (spectral diffusion, T^4 radiation and convection, sensor lag); its
+// transforms want more registers than the explicit step, so it runs at two waves per SIMD.
+template <int SPEC>
+__global__ __launch_bounds__(TH_THREADS, SPEC ? 2 : 4) void tg_thermal_kernel(const ThermalLaunch q) {
   constexpr int n = TH_N;
   const KParams& p = *q.kc;
   const ThermalParams& th = *q.th;
@@ -50,11 +137,22 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
   const int tid = threadIdx.x, x = tid % n, y = tid / n;
   const int E = p.E, L = p.L, T = p.T;
   const int64_t EL = (int64_t)E * L, ET = (int64_t)E * T;
-  __shared__ float ex[n * n * n];          // exchange buffer [z][y][x]
+  __shared__ float ex[n * n * (n + 1)];    // exchange buffer [z][y][x] (rows padded to 17 for the spectral step)
   __shared__ float cd[512];                // kappa * depth per taxel of the link
   __shared__ float top[n * n];
   __shared__ Pose lp, op;
   __shared__ int oid_s;
+  // the spectral step's DCT-II matrix, its transpose and the filter's correction per |m|^2
+  __shared__ __align__(16) float Cs[SPEC ? TH_N * TH_N : 4], Ct[SPEC ? TH_N * TH_N : 4];
+  __shared__ float hks[SPEC ? 3 * (TH_N - 1) * (TH_N - 1) + 1 : 1];
+  if (SPEC) {
+    for (int i = threadIdx.x; i < TH_N * TH_N; i += TH_THREADS) {
+      Cs[i] = th.dct[i];
+      Ct[(i % TH_N) * TH_N + i / TH_N] = th.dct[i];
+    }
+    for (int i = threadIdx.x; i < 3 * (TH_N - 1) * (TH_N - 1) + 1; i += TH_THREADS) hks[i] = th.hk[i];
+    __syncthreads();
+  }
   float* fld = th.fields + ((int64_t)e * th.F + f) * (n * n * n);
   float col[n];
 #pragma unroll
@@ -81,6 +179,10 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
       ++nmine;
     }
   const int tvox = tid < nl ? th.taxel_vox[jb + tid] : 0;   // top voxel of taxel tid (one per lane)
+  constexpr bool spec = SPEC != 0;
+  // measured reading of taxel tid (the sensor element lag), kept in a register over the launch
+  float tm = 0.f;
+  if (spec && th.lag > 0.f && tid < nl) tm = th.t_meas[(int64_t)e * T + jb + tid];
   for (int s = 0; s < q.n_steps; ++s) {
     // 1. poses of this step (only to recompute the depths)
     if (!q.depth && tid == 0) {
@@ -95,8 +197,12 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
       op.p[0] = os[0 * E + e]; op.p[1] = os[1 * E + e]; op.p[2] = os[2 * E + e];
       quat_to_R(os[3 * E + e], os[4 * E + e], os[5 * E + e], os[6 * E + e], op.R);
     }
+    if (spec) {
+      spectral_diffuse(Cs, Ct, hks, col, ex, tid);
+    } else {
 #pragma unroll
-    for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];
+      for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];
+    }
     __syncthreads();
     // 2. clean depth of the link's taxels: the readout's own output when the rollout writes it,
     //    else recomputed with the readout's FP32 sequence (the same value)
@@ -134,6 +240,24 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
       for (int k = 0; k < nl; ++k)
         if (th.taxel_vox[jb + k] == myvox) cv = cv + cd[k];
     }
+    if (spec) {
+      // 4'. the paper's order after the diffusion: source, contact conduction on the top voxel,
+      //     then radiation (T^4 in kelvin, as (T - Ta)(T_K + Ta_K)(T_K^2 + Ta_K^2)) and convection
+      //     from every face of the block
+      const float TaK = Tamb + 273.15f, TaK2 = TaK * TaK;
+#pragma unroll
+      for (int z = 0; z < n; ++z) {
+        float t = col[z] + g;
+        if (z == n - 1) t = t + cv * (Tobj - t);
+        const int faces = fxy + (z == 0) + (z == n - 1);
+        if (faces) {
+          const float d = t - Tamb, TK = t + 273.15f;
+          const float q4 = d * ((TK + TaK) * fmaf(TK, TK, TaK2));
+          t = t - (float)faces * fmaf(th.k_rad, q4, th.k_conv * d);
+        }
+        col[z] = t;
+      }
+    } else {
     // 4. explicit step from the old values (exchange buffer, and registers for z +- 1): the column
     //    is updated in place from the bottom, with the old value below carried in `below`
     float below = col[0];
@@ -152,11 +276,13 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
       below = t;
       col[z] = t + (r * (sum - 6.0f * t) + src);
     }
+    }
     top[myvox] = col[n - 1];
     __syncthreads();   // every read of ex and cd is done; top is complete
+    if (spec && th.lag > 0.f && tid < nl) tm = fmaf(th.lag, top[tvox] - tm, tm);
     if (q.temperature) {
       float* out = q.temperature + (int64_t)s * ET + (int64_t)e * T;
-      if (tid < nl) out[jb + tid] = top[tvox];
+      if (tid < nl) out[jb + tid] = spec && th.lag > 0.f ? tm : top[tvox];
       for (int k = tid + TH_THREADS; k < nl; k += TH_THREADS) out[jb + k] = top[th.taxel_vox[jb + k]];
       if (f == 0)   // the first field's workgroup clears the taxels of the non-thermal links
         for (int j = tid; j < T; j += TH_THREADS)
@@ -165,6 +291,7 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
   }
 #pragma unroll
   for (int z = 0; z < n; ++z) fld[(z * n + y) * n + x] = col[z];
+  if (spec && th.lag > 0.f && tid < nl) th.t_meas[(int64_t)e * T + jb + tid] = tm;
 }
 
 __global__ void tg_thermal_reset_kernel(const ThermalParams* thp, int E, const uint8_t* mask) {
@@ -176,6 +303,14 @@ __global__ void tg_thermal_reset_kernel(const ThermalParams* thp, int E, const u
   const int e = (int)(i / (th.F * NV));
   if (mask && !mask[e]) return;
   th.fields[i] = th.T0;
+}
+
+__global__ void tg_thermal_reset_meas_kernel(const ThermalParams* thp, int E, int T, const uint8_t* mask) {
+  const ThermalParams& th = *thp;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)E * T) return;
+  if (mask && !mask[i / T]) return;
+  th.t_meas[i] = th.T0;
 }
 
 }  // namespace tg

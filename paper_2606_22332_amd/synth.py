@@ -132,6 +132,9 @@ class ThermalParams:
     T0: float = 22.0
     T_amb: float = 22.0
     P_gen: float = 0.1
+    solver: int = 0                       # 0 explicit 7-point step, 1 the paper's spectral step
+    h_conv: float = 0.0                   # convection coefficient [W/m^2K] (solver 1)
+    lag_tau: float = 0.0                  # sensor element time constant [s] (solver 1; 0 = none)
 
 
 @dataclass
@@ -483,6 +486,13 @@ def nsdf_init(n_obj: int, seed: int) -> np.ndarray:
         o += 64 * fan_in + 64
     P[:, o:o + 64] = rng.uniform(-np.sqrt(6.0 / 64), np.sqrt(6.0 / 64), (n_obj, 64))
     return P.astype(np.float32)
+
+
+def surface_clouds(grids: List[Grid], n: int, seed: int) -> List[np.ndarray]:
+    """The tracked surface point cloud of each object (ProximityTaxel, App. A.6): n area-uniform
+    points on the analytic surface, object frame, generated in FP64 and rounded once to FP32."""
+    rng = np.random.default_rng(seed)
+    return [np.ascontiguousarray(_surface_points(g.shape, n, rng).astype(np.float32)) for g in grids]
 
 
 def _surface_points(s: dict, n: int, rng: np.random.Generator) -> np.ndarray:

@@ -119,6 +119,50 @@ def test_all_noise_knobs(torch_cuda):
     print("knobs", info)
 
 
+def test_quantisation_knob(torch_cuda):
+    """Noisy F/T quantised to q (App. A.8 sensor noise model: quantize(x, q) = q rint(x / q)).
+    Before rounding, the GPU's noisy value and the oracle's agree to the noisy bar (the Box-Muller
+    draws use the hardware log/sin/cos on the GPU and FP64 libm in the oracle, so they are not bit
+    for bit equal).  Rounding to q keeps that agreement except where the value sits within the bar
+    of a rounding boundary (x / q within eps of k + 1/2): there the two sides may round to
+    neighbouring steps.  So every quantised value must equal the oracle's, or differ by exactly
+    one step at a value that the oracle without quantisation puts within eps of a boundary."""
+    import dataclasses
+    sc = synth.make_scene("c2", num_envs=16, num_steps=6)
+    q = 2e-3
+    base = synth.NoiseParams(enabled=True, seed=77, drift_sigma=1e-3, white_sigma=5e-3, hyst_mode=1,
+                             tau_load_steps=2.0, tau_unload_steps=6.0, p_dead=0.02, xtalk_kind=1, xtalk_chi=0.05,
+                             eta_off=2e-4)
+    sc.noise = dataclasses.replace(base, quant_step=q)
+    inp = synth.make_inputs(sc)
+    g = run_gpu(sc, inp)
+    rq = oracle_ref(sc, inp)
+    sc_raw = dataclasses.replace(sc, noise=base)
+    rv = oracle_ref(sc_raw, inp)                 # the same noisy chain without the rounding
+    T = sc.layout.num_taxels
+    # everything except the quantised channel to the usual bars (bits and clean outputs exact)
+    parity.compare({k: v for k, v in g.items() if k not in ("ft_noisy", "link_sums_noisy")}, rq, T,
+                   link_offset=sc.layout.link_offset)
+    gb = parity.unpack_bits(g["bits_noisy"], T)
+    assert np.array_equal(gb, rq["bit_noisy"])
+    sigma = float(np.hypot(base.drift_sigma, base.white_sigma))
+    sf, st = parity.noisy_scale(rv, sigma)
+    scale = np.stack([sf] * 3 + [st] * 3, axis=1)            # [S,6,E,T] noisy bar scale per element
+    eps = parity.REL * np.maximum(scale, np.abs(rv["ft_noisy"]))
+    gq = g["ft_noisy"].astype(np.float64)
+    d = np.abs(gq - rq["ft_noisy"])
+    same = d <= 1e-9 * q
+    # one step apart, at a value that lies within eps of a rounding boundary
+    frac = np.abs(rv["ft_noisy"] / q - np.floor(rv["ft_noisy"] / q) - 0.5) * q
+    flip = (np.abs(d - q) <= 1e-6 * q) & (frac <= eps)
+    assert np.all(same | flip), np.argwhere(~(same | flip))[:5]
+    # the rounded values are whole steps, and the rounding moved them by at most half a step
+    assert np.all(np.abs(gq / q - np.rint(gq / q)) <= 1e-3)
+    live = rq["ft_noisy"] != 0
+    assert np.all(np.abs(gq - rv["ft_noisy"])[live] <= 0.5 * q * (1 + 1e-3) + eps[live])
+    print(dict(elements=int(d.size), exact=float(same.mean()), boundary_flips=int((~same).sum())))
+
+
 def test_reset_subset_and_state_roundtrip(torch_cuda):
     from paper_2606_22332_amd import binding as B
     torch = torch_cuda
