@@ -427,6 +427,89 @@ def bench_prox(reps: int = 5) -> dict:
     return res
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def bench_audio(reps: int = 5) -> dict:
+    """The contact-audio sensor (App. E) on the hand's 5 fingertip links (4096 envs): the clean
+    100-step readout of the 4096-env x 200-taxel hand supplies taxel forces and contact normals;
+    each (env, fingertip) synthesises K = 240 samples per 5 ms step (48 kHz) through a 16-mode
+    plate bank of the env's object's material (wood, metal, glass).  The audio launch alone is
+    timed with HIP events (median of `reps`); the roofline is FP64 FMA issue: 6 flops per mode and
+    sample (two FMAs of the recurrence, one of the output sum)."""
+    import torch
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+    sc = synth.make_scene("c2")
+    inp = synth.make_inputs(sc)
+    lay = sc.layout
+    E, T, S, K = sc.num_envs, lay.num_taxels, inp.link_state.shape[0], 240
+    links = (1, 2, 3, 4, 5)
+    ranges = [(int(lay.link_offset[l]), int(lay.link_offset[l + 1])) for l in links]
+    ro = B.Readout(sc, B.TG_OUT_FT | B.TG_OUT_NORMAL)
+    d = B.to_device(inp)
+    ro.alloc_outputs(S)
+    ro.rollout(d, S)
+    ft, nm = ro.out["ft"], ro.out["normal"]
+    mats = synth.audio_materials(16, K / sc.dt)
+    material = (np.asarray(inp.obj_id[0]) % 3).astype(np.int32)
+    dmat = torch.from_numpy(material).cuda()
+    au = B.Audio(E, T, ranges, mats, 16, K, sc.dt, g_imp=1.0, g_scr=1.0, seed=sc.noise.seed)
+    stream = torch.cuda.current_stream()
+    out = au.rollout(ft, nm, dmat)
+    torch.cuda.synchronize()
+    first = out.clone()
+    ts = []
+    for _ in range(reps):
+        au.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        au.rollout(ft, nm, dmat, out=out)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    Ls = len(links)
+    samples = E * Ls * K * S
+    modes = np.array([len(m[0]) for m in mats])[material]
+    flops = 6.0 * float(modes.sum()) * Ls * K * S
+    sensor_taxels = sum(b - a for a, b in ranges)
+    hbm = S * E * (sensor_taxels * 6 * 4 + Ls * K * 4)
+    res = {"workload": f"c2 hand: {E} envs x {Ls} fingertip links ({sensor_taxels} taxels) x {S} steps, K = {K} "
+                       f"samples per {sc.dt * 1e3:.0f} ms step (48 kHz), 16-mode banks (wood, metal, glass), "
+                       "excited by the clean readout's forces and normals",
+           "ms_per_rollout": ms, "samples_per_s": samples / (ms * 1e-3), "dtype": "f64 (FP32 output)",
+           "roofline": {"bound": "alu", "achieved": flops / (ms * 1e-3) / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": flops / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS,
+                        "flops_per_launch": flops, "hbm_gbs": hbm / (ms * 1e-3) / 1e9,
+                        "kernel": "tg_audio_kernel"},
+           "repeatable_after_reset": bool(torch.equal(first, out)),
+           "active_fraction": float((out.abs().amax(dim=3) > 0).float().mean().item())}
+    try:
+        from oracle import audio as OA
+        envs = np.array([0, E - 1])
+        idx = torch.as_tensor(envs, device="cuda")
+        fts = ft[:, :, idx].cpu().numpy()
+        nms = nm[:, :, idx].cpu().numpy()
+        Fn = np.zeros((S, len(envs), Ls))
+        Ft = np.zeros_like(Fn)
+        for li, (a, b) in enumerate(ranges):
+            n_, t_ = OA.link_excitation(fts, nms, [a, b], [0])
+            Fn[:, :, li], Ft[:, :, li] = n_[:, :, 0], t_[:, :, 0]
+        ref = OA.contact_audio(Fn, Ft, material[envs], mats, 16, sc.dt, K, 1.0, 1.0, sc.noise.seed, env_ids=envs)
+        g = first[:, idx].cpu().numpy().astype(np.float64)
+        scale = np.abs(ref).max(axis=(0, 3), keepdims=True)
+        tol = 2.0 ** -24 * np.abs(ref) + 1e-9 * scale + 1e-30
+        res["fp64_check"] = {"envs": envs.tolist(), "max_err_over_bar": float((np.abs(g - ref) / tol).max()),
+                             "fp32_equal_fraction": float(np.mean(g == ref.astype(np.float32).astype(np.float64)))}
+    except ImportError:
+        pass
+    au.close()
+    ro.out = {}
+    ro.close()
+    return res
+
+
 def c4_summary(r: dict) -> dict:
     """The grid-vs-neural comparison of bench_c4, without the fields of a bench line."""
     keep = ("config", "grid_path", "speedup_vs_grid", "depth_err_um", "normal_err_deg", "training", "memory_MB")
@@ -447,7 +530,7 @@ def main():
     ap.add_argument("--readouts-per-block", type=int, default=0,
                     help="fix the work plan instead of autotuning (the profiles pin the autotuner's choice)")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", default="readout", choices=["readout", "c4", "proximity"])
+    ap.add_argument("--workload", default="readout", choices=["readout", "c4", "proximity", "audio"])
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--nsdf-samples", type=int, default=1 << 17)
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"])
@@ -459,6 +542,10 @@ def main():
     ap.add_argument("--grad-lambda", type=float, default=None,
                     help="weight of the L1 term on the network's input gradient against the grid's (0: off)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES")
+    ap.add_argument("--thermal-solver", type=int, default=0, choices=[0, 1],
+                    help="c5 only: 0 the explicit stencil, 1 the spectral step with T^4 radiation (App. D.1)")
+    ap.add_argument("--h-conv", type=float, default=0.0, help="c5, solver 1: convection coefficient [W/m^2K]")
+    ap.add_argument("--lag-tau", type=float, default=0.0, help="c5, solver 1: sensor element lag [s] (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -476,12 +563,17 @@ def main():
     if args.workload == "proximity":
         print(json.dumps(bench_prox()), flush=True)
         return
+    if args.workload == "audio":
+        print(json.dumps(bench_audio()), flush=True)
+        return
 
     import torch
     from paper_2606_22332_amd import binding as B
     from paper_2606_22332_amd import synth
 
     sc = synth.make_scene(args.config, num_envs=args.envs)
+    if sc.thermal is not None and args.thermal_solver:
+        sc.thermal.solver, sc.thermal.h_conv, sc.thermal.lag_tau = 1, args.h_conv, args.lag_tau
     t0 = time.perf_counter()
     inp = synth.make_inputs(sc)
     gen_s = time.perf_counter() - t0
@@ -537,7 +629,10 @@ def main():
         "config": {"workload": f"{sc.name}: {E} envs x {T} taxels ({L} links) x {S}-step rollout, grid SDF "
                                f"({len(sc.grids)} objects, {sc.grids[0].n}^3), "
                                + ("noisy, " + {0: "no", 1: "banded", 2: "dense BF16-MFMA"}[sc.noise.xtalk_kind]
-                                  + " crosstalk" if sc.noise.enabled else "clean"),
+                                  + " crosstalk" if sc.noise.enabled else "clean")
+                               + ("" if sc.thermal is None else
+                                  ", TemperatureGrid " + ("spectral" if sc.thermal.solver == 1 else "explicit")
+                                  + f" on {len(sc.thermal.field_links)} links"),
                    "envs": E, "taxels": T, "links": L, "steps_per_rollout": S,
                    "readouts_per_block_target": eb, "threads_per_block": threads,
                    "autotuned": tuned is not None, "graph": not args.no_graph},
@@ -571,6 +666,8 @@ def main():
         rec["c2_step"] = bench_c2_step()
         torch.cuda.empty_cache()
         rec["proximity"] = bench_prox()
+        torch.cuda.empty_cache()
+        rec["contact_audio"] = bench_audio()
         torch.cuda.empty_cache()
         a4 = argparse.Namespace(**vars(args))
         a4.envs, a4.steps = None, 5

@@ -78,15 +78,18 @@ def new_state(E, Ls, slots):
     return {"y1": np.zeros((E, Ls, slots)), "y2": np.zeros((E, Ls, slots)), "fn": np.zeros((E, Ls))}
 
 
-def contact_audio(Fn, Ft, material, banks, slots, dt, K, g_imp, g_scr, seed, step0=0, state=None):
+def contact_audio(Fn, Ft, material, banks, slots, dt, K, g_imp, g_scr, seed, step0=0, state=None, env_ids=None):
     """Fn, Ft [S][E][Ls] link excitations; material [E] bank index per env (out of range: silent);
     banks: list of (f, d, g).  state (new_state(...) or None: at rest) is updated in place.
-    Returns the samples [S][E][Ls][K]."""
+    env_ids [E]: the env index of each row in the noise counter (default 0..E-1, for a subset of
+    envs their indices in the full batch).  Returns the samples [S][E][Ls][K]."""
     Fn = np.asarray(Fn, np.float64)
     Ft = np.asarray(Ft, np.float64)
     S, E, Ls = Fn.shape
     if state is None:
         state = new_state(E, Ls, slots)
+    if env_ids is None:
+        env_ids = np.arange(E)
     dts = dt / K
     A1, A2, G = bank_coefficients(banks, slots, dts)
     zero = np.zeros(slots)
@@ -99,7 +102,7 @@ def contact_audio(Fn, Ft, material, banks, slots, dt, K, g_imp, g_scr, seed, ste
             y1, y2 = state["y1"][e, l].copy(), state["y2"][e, l].copy()
             fn_prev = state["fn"][e, l]
             for s in range(S):
-                xi = noise_block(seed, e, l, step0 + s, K)
+                xi = noise_block(seed, int(env_ids[e]), l, step0 + s, K)
                 imp = g_imp * max(0.0, Fn[s, e, l] - fn_prev)
                 amp = g_scr * Ft[s, e, l]
                 for k in range(K):

@@ -621,3 +621,96 @@ class Proximity:
             self.close()
         except Exception:
             pass
+
+
+class TgAudioMaterial(C.Structure):
+    _fields_ = [("num_modes", C.c_int32), ("freq", C.c_void_p), ("decay", C.c_void_p), ("gain", C.c_void_p)]
+
+
+class TgAudioConfig(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("num_envs", C.c_int32), ("num_taxels", C.c_int32),
+                ("num_sensor_links", C.c_int32), ("sensor_taxel_begin", C.c_void_p),
+                ("sensor_taxel_end", C.c_void_p), ("num_materials", C.c_int32), ("materials", C.c_void_p),
+                ("slots", C.c_int32), ("samples_per_step", C.c_int32), ("dt", C.c_double), ("g_imp", C.c_double),
+                ("g_scr", C.c_double), ("seed", C.c_uint64), ("lanes_per_pair", C.c_int32)]
+
+
+_audio_ready = False
+
+
+def _audio_lib() -> C.CDLL:
+    global _audio_ready
+    lib = load()
+    if not _audio_ready:
+        P = C.c_void_p
+        sig = {"tg_audio_create": ([P, P], C.c_int), "tg_audio_destroy": ([P], C.c_int),
+               "tg_audio_last_error": ([P], C.c_char_p), "tg_audio_reset": ([P, P], C.c_int),
+               "tg_audio_rollout": ([P, P, P, P, C.c_int64, C.c_int32, P, P], C.c_int)}
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _audio_ready = True
+    return lib
+
+
+class Audio:
+    """Contact-audio sensor on the sensor links of a taxel layout.  materials: list of (freq, decay,
+    gain) arrays; sensor_ranges: list of (first taxel, one past the last).  Buffers are torch
+    tensors on the current device; this class only passes their pointers to the library."""
+
+    def __init__(self, num_envs, num_taxels, sensor_ranges, materials, slots, samples_per_step, dt,
+                 g_imp=1.0, g_scr=1.0, seed=0, lanes_per_pair=0):
+        import torch
+        self._torch = torch
+        self.lib = _audio_lib()
+        self.E, self.T, self.K = int(num_envs), int(num_taxels), int(samples_per_step)
+        self.Ls = len(sensor_ranges)
+        begin = np.ascontiguousarray([r[0] for r in sensor_ranges], np.int32)
+        end = np.ascontiguousarray([r[1] for r in sensor_ranges], np.int32)
+        keep = [begin, end]
+        mats = (TgAudioMaterial * max(len(materials), 1))()
+        for i, (f, d, g) in enumerate(materials):
+            arrs = [np.ascontiguousarray(x, np.float64).reshape(-1) for x in (f, d, g)]
+            keep += arrs
+            mats[i].num_modes = arrs[0].shape[0]
+            mats[i].freq, mats[i].decay, mats[i].gain = (a.ctypes.data for a in arrs)
+        cfg = TgAudioConfig(ABI_VERSION, self.E, self.T, self.Ls, begin.ctypes.data, end.ctypes.data, len(materials),
+                            C.cast(mats, C.c_void_p).value, int(slots), self.K, float(dt), float(g_imp), float(g_scr),
+                            int(seed), int(lanes_per_pair))
+        h = C.c_void_p()
+        rc = self.lib.tg_audio_create(C.byref(cfg), C.byref(h))
+        if rc != 0:
+            raise TgError(f"tg_audio_create: {self.lib.tg_status_string(rc).decode()}: "
+                          f"{self.lib.tg_audio_last_error(None).decode()}")
+        self.h = h
+
+    def rollout(self, ft, normal, material, step0=0, out=None, stream=None):
+        """ft [S][6][E][T], normal [S][3][E][T] (float32), material [E] (int32), all on the device.
+        Returns the samples [S][E][Ls][K]."""
+        torch = self._torch
+        S = ft.shape[0]
+        if out is None:
+            out = torch.empty((S, self.E, self.Ls, self.K), dtype=torch.float32, device=ft.device)
+        rc = self.lib.tg_audio_rollout(self.h, ft.data_ptr(), normal.data_ptr(), material.data_ptr(), int(step0),
+                                       int(S), out.data_ptr(), _stream_ptr(stream))
+        if rc != 0:
+            raise TgError(f"tg_audio_rollout: {self.lib.tg_status_string(rc).decode()}: "
+                          f"{self.lib.tg_audio_last_error(self.h).decode()}")
+        return out
+
+    def reset(self, stream=None):
+        rc = self.lib.tg_audio_reset(self.h, _stream_ptr(stream))
+        if rc != 0:
+            raise TgError(f"tg_audio_reset: {self.lib.tg_audio_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.tg_audio_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -49,79 +49,107 @@ struct ThermalLaunch {
                                // kernel before this launch), or null: recomputed here
 };
 
-// 16-point transforms with the DCT-II matrix (forward y = C v, inverse y = C^T v).  The matrix and
-// its transpose sit in LDS (Cs, Ct), read row by row with uniform addresses (one broadcast 16-byte
-// read per four coefficients); the input v is in registers.
-__device__ __forceinline__ float dct16_row(const float* Cr, const float v[TH_N]) {
-  const float4* row = (const float4*)Cr;
-  float a = 0.f;
-#pragma unroll
-  for (int q = 0; q < TH_N / 4; ++q) {
-    const float4 c = row[q];
-    a = fmaf(c.x, v[4 * q], a);
-    a = fmaf(c.y, v[4 * q + 1], a);
-    a = fmaf(c.z, v[4 * q + 2], a);
-    a = fmaf(c.w, v[4 * q + 3], a);
-  }
-  return a;
-}
-// All 16 outputs written to LDS at dst[m * stride]: a rolled loop over the outputs keeps only v
-// and one accumulator live.
-__device__ __forceinline__ void dct16_to_lds(const float* Cr, const float v[TH_N], float* dst, int stride) {
-#pragma unroll 1
-  for (int m = 0; m < TH_N; ++m) dst[m * stride] = dct16_row(Cr + m * TH_N, v);
-}
-
-// The paper's spectral diffusion step (App. D.1) on the block held as z-columns `col` (thread (x,y)).
-// The mirror-padded FFT filter 1 / (1 + a k^2) is diagonal in the DCT-II basis of the block, with
+// The paper's spectral diffusion step (App. D.1) on a block held as z-columns `col` (thread (x,y)).
+// The mirror-padded FFT filter 1 / (1 + a k^2) is diagonal in the DCT-II basis C of the block, with
 // k^2 = (pi / (n dx))^2 (mx^2 + my^2 + mz^2).  It is applied in the equal correction form
 //   T' = T - C3^T (h * C3 T),   h = a k^2 / (1 + a k^2) <= a k_max^2,
-// so the FP32 rounding of the transforms multiplies only the small correction.  C3 is separable:
-// each axis in turn, the data going through the exchange buffer (rows padded to 17 floats,
-// conflict-free), thread (x, y) for z, (x, mz) for y, (my, mz) for x.
-__device__ __forceinline__ void spectral_diffuse(const float* Cs, const float* Ct, const float* hk, float col[TH_N],
-                                                 float* ex, int tid) {
-  constexpr int n = TH_N, RS = TH_N + 1;   // padded row stride
+// so the FP32 rounding of the transforms multiplies only the small correction.  C3 is separable,
+// and each axis is a 16 x 16 matrix times a 16 x 256 matrix: FP32 MFMA 16x16x4, 64 per axis and
+// block, 16 per wave.  The block sits in the exchange buffer ex[z][y][x] (rows padded to 17 floats,
+// planes 272): a contraction reads its B operand (4 rows of the contracted axis by 16 columns)
+// straight from it and writes its 16 x 16 result back in place, each wave owning 4 whole tiles, so
+// only the change of axis needs a barrier.  The forward x transform's result feeds the inverse x
+// transform from registers: its 4 output rows per lane group are the inverse's K slices when the
+// inverse contracts mx in the order (4 g + r) over (register r, lane group g).
+//   lane l = 16 g + c:  A[i = c][k = g],  B[k = g][j = c],  D[i = 4 g + r][j = c] (register r)
+struct DctOperands {   // A operands of the DCT-II matrix C (forward) and C^T (inverse), per lane
+  float fwd[4];        // C[c][4 kb + g]       (K slice kb: k = 4 kb + g)
+  float inv[4];        // C^T[c][4 kb + g]
+  float inv_chain[4];  // C^T[c][4 g + r]      (K slice r: k = 4 g + r)
+};
+__device__ __forceinline__ DctOperands dct_operands(const float* dct, int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  DctOperands o;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    o.fwd[k] = dct[c * TH_N + 4 * k + g];
+    o.inv[k] = dct[(4 * k + g) * TH_N + c];
+    o.inv_chain[k] = dct[(4 * g + k) * TH_N + c];
+  }
+  return o;
+}
+typedef float dct_acc __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ dct_acc mfma4(float a, float b, dct_acc acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+// One axis of a wave's 4 tiles: tile t reads B slice kb at ex[base(t) + (4 kb + g) * ks + c * cs]
+// and writes D row 4 g + r at ex[base(t) + (4 g + r) * ks + c * cs] (ks: stride of the contracted
+// axis, cs: of the column axis).
+__device__ __forceinline__ void dct_axis(float* ex, const float A[4], int base0, int tstride, int ks, int cs,
+                                         int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  dct_acc d[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const float* src = ex + base0 + t * tstride + c * cs;
+    dct_acc acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) acc = mfma4(A[kb], src[(4 * kb + g) * ks], acc);
+    d[t] = acc;
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    float* dst = ex + base0 + t * tstride + c * cs;
+    dst[(4 * g + 0) * ks] = d[t].x;
+    dst[(4 * g + 1) * ks] = d[t].y;
+    dst[(4 * g + 2) * ks] = d[t].z;
+    dst[(4 * g + 3) * ks] = d[t].w;
+  }
+}
+__device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const float* hk, float col[TH_N], float* ex,
+                                                 int tid) {
+  constexpr int n = TH_N, RS = TH_N + 1, PS = TH_N * (TH_N + 1);
   const int x = tid % n, y = tid / n;
-  float v[n];
-  // forward z: thread (x, y) -> ex[mz][y][x]
-  dct16_to_lds(Cs, col, ex + y * RS + x, n * RS);
-  __syncthreads();
-  // forward y: thread (x, mz) reads ex[mz][.][x], writes ex[mz][my][x]
+  const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
 #pragma unroll
-  for (int i = 0; i < n; ++i) v[i] = ex[(y * n + i) * RS + x];
+  for (int z = 0; z < n; ++z) ex[z * PS + y * RS + x] = col[z];
   __syncthreads();
-  dct16_to_lds(Cs, v, ex + y * n * RS + x, RS);
+  // forward z: tiles y = 4 w + t; K = z (plane stride), columns x
+  dct_axis(ex, C.fwd, 4 * w * RS, RS, PS, 1, lane);
   __syncthreads();
-  // forward x, scale by h, inverse x: thread (my, mz) on row ex[mz][my][.]
-  {
-    const int my = x, mz = y;
-    float* rowp = ex + (mz * n + my) * RS;
+  // forward y: planes mz = 4 w + t; K = y (row stride), columns x
+  dct_axis(ex, C.fwd, 4 * w * PS, PS, RS, 1, lane);
+  __syncthreads();
+  // forward x, scale by h, inverse x: planes mz = 4 w + t; K = x, columns my
 #pragma unroll
-    for (int i = 0; i < n; ++i) v[i] = rowp[i];
-    float w[n];
+  for (int t = 0; t < 4; ++t) {
+    const int mz = 4 * w + t;
+    float* pl = ex + mz * PS;
+    dct_acc acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int mx = 0; mx < n; ++mx) {
-      w[mx] = dct16_row(Cs + mx * n, v) * hk[mx * mx + my * my + mz * mz];
-      __builtin_amdgcn_sched_barrier(0);   // one row's coefficients live at a time
-    }
-    dct16_to_lds(Ct, w, rowp, 1);
+    for (int kb = 0; kb < 4; ++kb) acc = mfma4(C.fwd[kb], pl[c * RS + 4 * kb + g], acc);
+    // acc: row mx = 4 g + r, column my = c
+    const int b2 = c * c + mz * mz;
+    dct_acc inv = {0.f, 0.f, 0.f, 0.f};
+    inv = mfma4(C.inv_chain[0], acc.x * hk[(4 * g + 0) * (4 * g + 0) + b2], inv);
+    inv = mfma4(C.inv_chain[1], acc.y * hk[(4 * g + 1) * (4 * g + 1) + b2], inv);
+    inv = mfma4(C.inv_chain[2], acc.z * hk[(4 * g + 2) * (4 * g + 2) + b2], inv);
+    inv = mfma4(C.inv_chain[3], acc.w * hk[(4 * g + 3) * (4 * g + 3) + b2], inv);
+    // inv: row x = 4 g + r, column my = c (every read of the plane is behind it)
+    pl[c * RS + 4 * g + 0] = inv.x;
+    pl[c * RS + 4 * g + 1] = inv.y;
+    pl[c * RS + 4 * g + 2] = inv.z;
+    pl[c * RS + 4 * g + 3] = inv.w;
   }
   __syncthreads();
-  // inverse y: thread (x, mz)
-#pragma unroll
-  for (int m = 0; m < n; ++m) v[m] = ex[(y * n + m) * RS + x];
+  // inverse y: planes mz = 4 w + t; K = my, columns x
+  dct_axis(ex, C.inv, 4 * w * PS, PS, RS, 1, lane);
   __syncthreads();
-  dct16_to_lds(Ct, v, ex + y * n * RS + x, RS);
+  // inverse z: tiles y = 4 w + t; K = mz, columns x
+  dct_axis(ex, C.inv, 4 * w * RS, RS, PS, 1, lane);
   __syncthreads();
-  // inverse z: thread (x, y); subtract the correction
 #pragma unroll
-  for (int m = 0; m < n; ++m) v[m] = ex[(m * n + y) * RS + x];
-#pragma unroll
-  for (int z = 0; z < n; ++z) {
-    col[z] = col[z] - dct16_row(Ct + z * n, v);
-    __builtin_amdgcn_sched_barrier(0);
-  }
+  for (int z = 0; z < n; ++z) col[z] = col[z] - ex[z * PS + y * RS + x];
   __syncthreads();   // the exchange buffer is free again
 }
 
@@ -142,14 +170,11 @@ __global__ __launch_bounds__(TH_THREADS, SPEC ? 2 : 4) void tg_thermal_kernel(co
   __shared__ float top[n * n];
   __shared__ Pose lp, op;
   __shared__ int oid_s;
-  // the spectral step's DCT-II matrix, its transpose and the filter's correction per |m|^2
-  __shared__ __align__(16) float Cs[SPEC ? TH_N * TH_N : 4], Ct[SPEC ? TH_N * TH_N : 4];
+  // the spectral step's filter correction per |m|^2 and the DCT-II operands of this lane
   __shared__ float hks[SPEC ? 3 * (TH_N - 1) * (TH_N - 1) + 1 : 1];
+  DctOperands dcto;
   if (SPEC) {
-    for (int i = threadIdx.x; i < TH_N * TH_N; i += TH_THREADS) {
-      Cs[i] = th.dct[i];
-      Ct[(i % TH_N) * TH_N + i / TH_N] = th.dct[i];
-    }
+    dcto = dct_operands(th.dct, tid & 63);
     for (int i = threadIdx.x; i < 3 * (TH_N - 1) * (TH_N - 1) + 1; i += TH_THREADS) hks[i] = th.hk[i];
     __syncthreads();
   }
@@ -198,7 +223,7 @@ __global__ __launch_bounds__(TH_THREADS, SPEC ? 2 : 4) void tg_thermal_kernel(co
       quat_to_R(os[3 * E + e], os[4 * E + e], os[5 * E + e], os[6 * E + e], op.R);
     }
     if (spec) {
-      spectral_diffuse(Cs, Ct, hks, col, ex, tid);
+      spectral_diffuse(dcto, hks, col, ex, tid);
     } else {
 #pragma unroll
       for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];

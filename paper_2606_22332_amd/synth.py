@@ -565,3 +565,70 @@ def nsdf_pairs(points: np.ndarray, delta: float, seed: int) -> np.ndarray:
     out[:, 0::2] = points
     out[:, 1::2] = (points.astype(np.float64) + delta * random_unit(rng, n_obj * n).reshape(n_obj, n, 3)).astype(np.float32)
     return out
+
+
+# ---------------------------------------------------------------------------------------------
+# Contact-audio inputs: material banks and taxel excitations
+# ---------------------------------------------------------------------------------------------
+# Preset banks from the textbook modes of a simply supported rectangular plate (a x b x h):
+#   f_mn = (pi / 2) sqrt(D / (rho h)) ((m / a)^2 + (n / b)^2),  D = E h^3 / (12 (1 - nu^2)),
+# Rayleigh damping d = (alpha + beta w^2) / 2 and gains sin(m pi x0 / a) sin(n pi y0 / b) at a
+# strike point; the lowest modes below the Nyquist frequency of the sample rate are kept.
+AUDIO_PRESETS = {   # Young's modulus [Pa], density [kg/m^3], Poisson ratio, Rayleigh alpha [1/s], beta [s]
+    "wood": (10e9, 600.0, 0.30, 60.0, 2e-7),
+    "metal": (200e9, 7800.0, 0.29, 4.0, 1e-9),
+    "glass": (70e9, 2500.0, 0.22, 10.0, 5e-9),
+}
+
+
+def audio_material(name: str, n_modes: int, fs: float, plate=(0.30, 0.20, 0.003), strike=(0.37, 0.41)):
+    E_y, rho, nu, alpha, beta = AUDIO_PRESETS[name]
+    a, b, h = plate
+    D = E_y * h ** 3 / (12.0 * (1.0 - nu * nu))
+    c = 0.5 * np.pi * np.sqrt(D / (rho * h))
+    modes = sorted((c * ((m / a) ** 2 + (n / b) ** 2), m, n) for m in range(1, 40) for n in range(1, 40))
+    modes = [x for x in modes if x[0] < 0.45 * fs][:n_modes]
+    f = np.array([x[0] for x in modes])
+    w = 2.0 * np.pi * f
+    d = 0.5 * (alpha + beta * w * w)
+    g = np.array([np.sin(m * np.pi * strike[0]) * np.sin(n * np.pi * strike[1]) for _, m, n in modes])
+    return f, d, g
+
+
+def audio_materials(n_modes: int = 16, fs: float = 48000.0):
+    return [audio_material(k, n_modes, fs) for k in ("wood", "metal", "glass")]
+
+
+def audio_excitation(num_steps: int, num_envs: int, num_taxels: int, seed: int, contact_frac: float = 0.3,
+                     mu: float = 0.5):
+    """Taxel forces and contact normals with the structure of the kinematic law: where a taxel is
+    in contact, f = F_n m + f_t with m a unit normal, f_t normal to m and |f_t| <= mu F_n; elsewhere
+    f = 0 and m = 0.  F_n follows a clipped sinusoid per taxel, so contacts rise, hold and release.
+    The torque channels hold a marker (99) where in contact.
+    Returns (ft [S][6][E][T], normal [S][3][E][T]), float32."""
+    rng = np.random.default_rng(seed)
+    S, E, T = num_steps, num_envs, num_taxels
+    f32 = np.float32
+    m = rng.normal(size=(3, E, T)).astype(f32)
+    m /= np.linalg.norm(m, axis=0, keepdims=True)
+    amp = rng.uniform(0.5, 3.0, (E, T)).astype(f32)
+    ph = rng.uniform(0, 2 * np.pi, (E, T)).astype(f32)
+    w = rng.uniform(0.2, 1.5, (E, T)).astype(f32)
+    bias = (rng.uniform(-1.0, 1.0, (E, T)) + (contact_frac - 0.5) * 2.0).astype(f32)
+    # a tangent direction per taxel normal to m, turning with the step
+    a = rng.normal(size=(3, E, T)).astype(f32)
+    a -= np.sum(a * m, axis=0, keepdims=True) * m
+    a /= np.maximum(np.linalg.norm(a, axis=0, keepdims=True), f32(1e-12))
+    b = np.cross(m, a, axis=0)
+    ft = np.zeros((S, 6, E, T), f32)
+    normal = np.zeros((S, 3, E, T), f32)
+    for s in range(S):
+        fn = np.maximum(f32(0), amp * np.sin(w * f32(s) + ph) + bias * amp)
+        inc = fn > 0
+        ang = rng.uniform(0, 2 * np.pi, (E, T)).astype(f32)
+        tm = f32(mu) * fn * rng.uniform(0.0, 1.0, (E, T)).astype(f32)
+        f = fn * m + tm * (np.cos(ang) * a + np.sin(ang) * b)
+        ft[s, 0:3] = np.where(inc, f, f32(0))
+        ft[s, 3:6] = np.where(inc, f32(99.0), f32(0))
+        normal[s] = np.where(inc, m, f32(0))
+    return ft, normal

@@ -1,0 +1,166 @@
+"""Contact-audio sensor (include/tg_audio.h) against the FP64 oracle, through the C ABI.
+
+Both sides run the resonators and the excitation in FP64 on the same FP32 inputs (taxel forces and
+contact normals) and the same FP64 bank parameters; the scrape noise is exact in FP32 on both.
+They differ only in FP64 rounding order (the kernel fuses multiply-adds and sums the lanes' parts
+pairwise), which the resonators amplify by at most sum_m |h[m]| <= 1 / ((1 - r) sin theta) (about
+1e5 for the slowest-decaying presets), far below FP32 resolution.  The kernel rounds each sample
+once to FP32, so the bar per sample is
+  |gpu - ref| <= 2^-24 |ref| (the rounding) + 1e-9 max|ref| over that (env, link) (FP64 order),
+and in practice most samples are the FP32 rounding of the oracle's value.
+
+Inputs: forces and normals with the kinematic law's structure (contacts rising, holding and
+releasing; friction within mu F_n), plate-mode banks of wood, metal and glass, ragged env and
+link counts, a ragged K, silent and out-of-range materials, each lane layout, two calls in a row
+(state carried over), reset, and the benchmark's full-size launch on sampled pairs.
+"""
+import numpy as np
+import pytest
+
+from oracle import audio as OA
+from paper_2606_22332_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_case(E, T, S, seed):
+    return synth.audio_excitation(S, E, T, seed)
+
+
+def gpu_run(torch, E, T, ranges, mats, slots, K, dt, ft, nm, material, calls=(None,), lanes=0, g_imp=0.7,
+            g_scr=0.2, seed=0x5EED, reset_before=None):
+    from paper_2606_22332_amd import binding as B
+    au = B.Audio(E, T, ranges, mats, slots, K, dt, g_imp=g_imp, g_scr=g_scr, seed=seed, lanes_per_pair=lanes)
+    dft, dnm = torch.from_numpy(ft).cuda(), torch.from_numpy(nm).cuda()
+    dmat = torch.from_numpy(np.ascontiguousarray(material, np.int32)).cuda()
+    outs = []
+    s0 = 0
+    S = ft.shape[0]
+    bounds = [S] if calls == (None,) else list(calls)
+    for i, s1 in enumerate(bounds):
+        if reset_before is not None and i == reset_before:
+            au.reset()
+        outs.append(au.rollout(dft[s0:s1].contiguous(), dnm[s0:s1].contiguous(), dmat, step0=s0).cpu().numpy())
+        s0 = s1
+    torch.cuda.synchronize()
+    au.close()
+    return np.concatenate(outs, 0)
+
+
+def oracle_run(ft, nm, ranges, mats, slots, K, dt, material, g_imp=0.7, g_scr=0.2, seed=0x5EED, envs=None):
+    Fn = np.zeros((ft.shape[0], ft.shape[2], len(ranges)))
+    Ft = np.zeros_like(Fn)
+    for li, (b, e) in enumerate(ranges):
+        n, t = OA.link_excitation(ft, nm, [b, e], [0])
+        Fn[:, :, li], Ft[:, :, li] = n[:, :, 0], t[:, :, 0]
+    if envs is not None:
+        Fn, Ft, material = Fn[:, envs], Ft[:, envs], np.asarray(material)[envs]
+    return OA.contact_audio(Fn, Ft, material, mats, slots, dt, K, g_imp, g_scr, seed, env_ids=envs), Fn, Ft
+
+
+def check(g, ref):
+    scale = np.abs(ref).max(axis=(0, 3), keepdims=True)
+    tol = 2.0 ** -24 * np.abs(ref) + 1e-9 * scale + 1e-30
+    err = np.abs(g.astype(np.float64) - ref)
+    info = dict(max_ratio=float((err / tol).max()), exact_fp32=float(np.mean(g == ref.astype(np.float32))),
+                rms=float(np.sqrt(np.mean(ref ** 2))), peak=float(np.abs(ref).max()))
+    assert np.all(err <= tol), info
+    return info
+
+
+RANGES = [(0, 7), (7, 19), (25, 30)]       # ragged sensor links of a 30-taxel layout (19..25 unused)
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 2, 4])
+def test_parity_each_lane_layout(torch_cuda, lanes):
+    E, T, S, K, dt = 7, 30, 5, 240, 0.005
+    mats = synth.audio_materials(8 if lanes == 1 else 16, K / dt)
+    slots = 8 if lanes == 1 else 16
+    ft, nm = make_case(E, T, S, seed=11)
+    material = np.array([0, 1, 2, -1, 1, 7, 0])            # -1 and 7: silent
+    g = gpu_run(torch_cuda, E, T, RANGES, mats, slots, K, dt, ft, nm, material, lanes=lanes)
+    ref, Fn, Ft = oracle_run(ft, nm, RANGES, mats, slots, K, dt, material)
+    info = check(g, ref)
+    print(dict(lanes=lanes, **info))
+    assert np.all(g[:, [3, 5]] == 0) and info["peak"] > 0
+    assert (np.diff(Fn, axis=0) > 0).any() and (Ft > 0).any()           # impacts and scrapes both occur
+
+
+@pytest.mark.parametrize("K", [1, 37, 1024])
+def test_ragged_and_extreme_block_lengths(torch_cuda, K):
+    E, T, S, dt = 5, 30, 3, 0.005
+    mats = synth.audio_materials(16, 48000.0)
+    ft, nm = make_case(E, T, S, seed=12)
+    material = np.array([2, 1, 0, 1, 2])
+    g = gpu_run(torch_cuda, E, T, RANGES, mats, 16, K, dt, ft, nm, material)
+    ref, _, _ = oracle_run(ft, nm, RANGES, mats, 16, K, dt, material)
+    print(dict(K=K, **check(g, ref)))
+
+
+def test_state_carries_over_calls_and_reset(torch_cuda):
+    E, T, S, K, dt = 6, 30, 6, 96, 0.004
+    mats = synth.audio_materials(12, K / dt)
+    ft, nm = make_case(E, T, S, seed=13)
+    material = np.array([0, 1, 2, 0, 1, 2])
+    g = gpu_run(torch_cuda, E, T, RANGES, mats, 12, K, dt, ft, nm, material, calls=(2, 3, 6))
+    ref, _, _ = oracle_run(ft, nm, RANGES, mats, 12, K, dt, material)
+    print(check(g, ref))
+    # a reset before the second call: that call starts from rest, as a fresh oracle run of its steps
+    g2 = gpu_run(torch_cuda, E, T, RANGES, mats, 12, K, dt, ft, nm, material, calls=(2, 6), reset_before=1)
+    Fn = np.zeros((S, E, 3)); Ft = np.zeros_like(Fn)
+    for li, (b, e) in enumerate(RANGES):
+        n, t = OA.link_excitation(ft, nm, [b, e], [0])
+        Fn[:, :, li], Ft[:, :, li] = n[:, :, 0], t[:, :, 0]
+    ref2 = OA.contact_audio(Fn[2:], Ft[2:], material, mats, 12, dt, K, 0.7, 0.2, 0x5EED, step0=2)
+    print(check(g2[2:], ref2))
+
+
+def test_full_size_sampled(torch_cuda):
+    """The benchmark's launch: the 4096-env hand, 5 fingertip links (200 taxels), K = 240 at
+    48 kHz, 16-slot banks, 100 steps; checked on sampled envs."""
+    torch = torch_cuda
+    sc = synth.make_scene("c2")
+    lay = sc.layout
+    ranges = [(int(lay.link_offset[l]), int(lay.link_offset[l + 1])) for l in (1, 2, 3, 4, 5)]
+    E, T, S, K, dt = sc.num_envs, lay.num_taxels, 100, 240, sc.dt
+    mats = synth.audio_materials(16, K / dt)
+    ft, nm = synth.audio_excitation(S, E, T, seed=21)
+    material = (np.arange(E) % 3).astype(np.int32)
+    g = gpu_run(torch, E, T, ranges, mats, 16, K, dt, ft, nm, material)
+    envs = np.array([0, 1, 2047, 4095])
+    ref, _, _ = oracle_run(ft, nm, ranges, mats, 16, K, dt, material, envs=envs)
+    print(check(g[:, envs], ref))
+
+
+def test_rejects_bad_configurations(torch_cuda):
+    from paper_2606_22332_amd import binding as B
+    mats = synth.audio_materials(4, 48000.0)
+    ok = dict(num_envs=2, num_taxels=30, sensor_ranges=RANGES, materials=mats, slots=4, samples_per_step=64,
+              dt=0.005)
+    B.Audio(**ok).close()
+    for bad in (dict(samples_per_step=0), dict(samples_per_step=1025), dict(slots=33), dict(slots=3),
+                dict(dt=0.0), dict(sensor_ranges=[(5, 31)]), dict(sensor_ranges=[(6, 5)]),
+                dict(materials=[(np.array([100.0]), np.array([-1.0]), np.array([1.0]))]),
+                dict(materials=[(np.array([np.nan]), np.array([1.0]), np.array([1.0]))]),
+                dict(lanes_per_pair=3)):
+        kw = {**ok, **bad}
+        with pytest.raises(B.TgError):
+            B.Audio(**kw)
+    import torch
+    au = B.Audio(**ok)
+    ft = torch.zeros((2, 6, 2, 30), device="cuda")
+    nm = torch.zeros((2, 3, 2, 30), device="cuda")
+    mat = torch.zeros(2, dtype=torch.int32, device="cuda")
+    out = torch.empty((2 * 2 * 3 * 64 + 1,), device="cuda")
+    from paper_2606_22332_amd.binding import TgError
+    with pytest.raises(TgError):
+        au.rollout(ft, nm, mat, out=out[1:].view(2, 2, 3, 64))          # misaligned output
+    au.close()

@@ -139,3 +139,13 @@ def test_silent_slots_and_out_of_range_material():
     # padding the bank with silent slots changes nothing audible
     one = run(Fn, Ft, banks, 0.005, 32, 1.0, 1.0, seed=4, material=np.array([-1, 0, 5]), slots=1)
     np.testing.assert_allclose(out, one, rtol=0, atol=1e-15)
+
+
+def test_env_subset_keeps_its_noise_streams():
+    rng = np.random.default_rng(9)
+    Fn, Ft = rng.uniform(0, 1, (2, 5, 1)), rng.uniform(0, 1, (2, 5, 1))
+    banks = [single(900.0, 30.0)]
+    full = run(Fn, Ft, banks, 0.005, 16, 1.0, 1.0, seed=2)
+    envs = np.array([1, 4])
+    sub = run(Fn[:, envs], Ft[:, envs], banks, 0.005, 16, 1.0, 1.0, seed=2, env_ids=envs)
+    np.testing.assert_array_equal(sub, full[:, envs])
