@@ -14,9 +14,10 @@
  * R_j + radius_rho (2u - 1), u = (2 (x >> 9) + 1) 2^-24 with x the first word of Philox4x32-10,
  * key = seed, counter (env, taxel, step, 9); a per-probe gain (optional) scales the six channels.
  *
- * The library keeps each cloud in a uniform cell grid in the object frame (cell edge = the largest
- * sensing radius plus radius_rho), points sorted by cell, so a query visits the 3 x 3 x 3 cells
- * around its centre as nine contiguous runs of points; the sums above are formed from two moments
+ * The library keeps each cloud in a uniform cell grid in the object frame (cell edge = half the
+ * largest sensing radius plus radius_rho), points sorted by cell, so a query visits, in each row of
+ * cells its sphere reaches, the cells under the sphere's chord as one contiguous run of points;
+ * the sums above are formed from two moments
  * accumulated over the visited points, sum P_ij and sum P_ij (p_i - q_j), which give every term of
  * f and tau (the velocity of a point is affine in its position).
  *

@@ -8,12 +8,15 @@
 //   f   = k rho S0 a + k_s rho [V - a (V . a)],  V = sum P v_p - S0 v_tax
 //   tau = k rho S1 x a
 // The neighbour search runs in the object frame (distances are rotation invariant): each cloud is
-// kept in a uniform cell grid, cell edge h >= every sensing radius, points sorted by cell, x
-// fastest, so the cells within R_j of a probe are at most 3 x 3 x 3 and each x-run of them is
-// one contiguous range of points.  One thread per (env, taxel) runs every step of the launch;
-// neighbouring lanes hold neighbouring taxels of one link, so they walk nearly the same cells and
-// their point loads hit the same L2 lines.  The visits are plain FP32 ALU work (a distance, a
-// compare, a square root and four multiply-adds per point inside the sphere).
+// kept in a uniform cell grid, cell edge h = half the largest sensing radius, points sorted by
+// cell, x fastest.  A probe visits the rows of cells (fixed y and z) that its sphere reaches; in
+// each row the sphere's chord fixes the x-range of cells, one contiguous range of points.  Against
+// cells as large as the radius (3 x 3 x 3 around the probe) this halves the points visited on the
+// hand's workload (about 775 instead of 1450 per probe, 378 of them inside the sphere).  One thread
+// per (env, taxel) runs every step of the launch; neighbouring lanes hold neighbouring taxels of
+// one link, so they walk nearly the same cells and their point loads hit the same L2 lines.  The
+// visits are plain FP32 ALU work (a distance, a compare, the hardware square root and four
+// multiply-adds per point inside the sphere).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,7 +41,7 @@ struct CloudDesc {      // one object's cell grid
   int32_t dims[3];      // cells per axis
   int32_t cell_off;     // first entry of this object's cell table (dims product + 1 entries)
   int32_t n_points;     // N_active of an env holding this object
-  int32_t pad;
+  float h;              // cell edge
 };
 
 struct ProxParams {
@@ -115,11 +118,14 @@ __global__ __launch_bounds__(PX_THREADS) void tg_prox_kernel(const ProxParams p,
         R = R > 0.f ? R : 0.f;
       }
       const float R2 = R * R;
+      // the culling below uses a radius grown by a relative 1e-5 (and 0.1 um), so rounding never
+      // drops a row or cell that holds a point inside the sphere; the point test is exact
+      const float Rc = fmaf(R, 1.00001f, 1e-7f), Rc2 = Rc * Rc;
       int lo[3], hi[3];
       bool empty = !(R > 0.f);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        const float u0 = (qo[i] - R - cd.origin[i]) * cd.hinv, u1 = (qo[i] + R - cd.origin[i]) * cd.hinv;
+        const float u0 = (qo[i] - Rc - cd.origin[i]) * cd.hinv, u1 = (qo[i] + Rc - cd.origin[i]) * cd.hinv;
         // NaN or entirely outside the grid: no points in range
         if (!(u1 >= 0.f) || !(u0 < (float)cd.dims[i])) empty = true;
         lo[i] = u0 > 0.f ? (int)u0 : 0;
@@ -127,16 +133,27 @@ __global__ __launch_bounds__(PX_THREADS) void tg_prox_kernel(const ProxParams p,
       }
       if (!empty) {
         const int32_t* cs = p.cells + cd.cell_off;
-        for (int cz = lo[2]; cz <= hi[2]; ++cz)
+        for (int cz = lo[2]; cz <= hi[2]; ++cz) {
+          const float zl = fmaf((float)cz, cd.h, cd.origin[2]);
+          const float ez = fmaxf(fmaxf(zl - qo[2], qo[2] - (zl + cd.h)), 0.f);
           for (int cy = lo[1]; cy <= hi[1]; ++cy) {
+            const float yl = fmaf((float)cy, cd.h, cd.origin[1]);
+            const float ey = fmaxf(fmaxf(yl - qo[1], qo[1] - (yl + cd.h)), 0.f);
+            const float c2 = Rc2 - fmaf(ey, ey, ez * ez);
+            if (!(c2 > 0.f)) continue;
+            const float half = __builtin_amdgcn_sqrtf(c2);
+            const float x0 = (qo[0] - half - cd.origin[0]) * cd.hinv, x1 = (qo[0] + half - cd.origin[0]) * cd.hinv;
+            const int ax = x0 > (float)lo[0] ? (int)x0 : lo[0];
+            const int bx = x1 < (float)hi[0] ? (int)x1 : hi[0];
+            if (ax > bx) continue;
             const int row = (cz * cd.dims[1] + cy) * cd.dims[0];
-            const int b = cs[row + lo[0]], t = cs[row + hi[0] + 1];
+            const int b = cs[row + ax], t = cs[row + bx + 1];
             for (int i = b; i < t; ++i) {
               const float4 pt = p.pts[i];
               const float dx = pt.x - qo[0], dy = pt.y - qo[1], dz = pt.z - qo[2];
               const float d2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
               if (d2 < R2) {
-                const float w = R - sqrtf(d2);
+                const float w = R - __builtin_amdgcn_sqrtf(d2);
                 S0 += w;
                 S1[0] = fmaf(w, dx, S1[0]);
                 S1[1] = fmaf(w, dy, S1[1]);
@@ -144,6 +161,7 @@ __global__ __launch_bounds__(PX_THREADS) void tg_prox_kernel(const ProxParams p,
               }
             }
           }
+        }
       }
     }
     float f[3] = {0.f, 0.f, 0.f}, tau[3] = {0.f, 0.f, 0.f};
@@ -235,8 +253,8 @@ tg_status tg_prox_create(const tg_prox_config* cfg, tg_prox** out) {
       std::memcpy(&lf, &li, 4);
       tb[j] = make_float4(cfg->taxel_normal[3 * j], cfg->taxel_normal[3 * j + 1], cfg->taxel_normal[3 * j + 2], lf);
     }
-  // cell edge: the largest radius a query can take (radius noise included), at least 0.1 mm
-  const float h = std::max(rmax + cfg->radius_rho, 1e-4f);
+  // cell edge: half the largest radius a query can take (radius noise included), at least 0.1 mm
+  const float h = std::max(0.5f * (rmax + cfg->radius_rho), 1e-4f);
   std::vector<CloudDesc> cds(NO);
   std::vector<int32_t> cells;
   std::vector<float4> pts;
@@ -263,7 +281,7 @@ tg_status tg_prox_create(const tg_prox_config* cfg, tg_prox** out) {
     d.hinv = 1.0f / h;
     d.cell_off = (int32_t)cells.size();
     d.n_points = c.num_points;
-    d.pad = 0;
+    d.h = h;
     // counting sort of the points by cell (x fastest)
     std::vector<int32_t> cid(c.num_points), cnt(ncell + 1, 0);
     for (int i = 0; i < c.num_points; ++i) {
