@@ -16,7 +16,7 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile the oracle (contraction off, no fast-math, OpenMP)."""
     srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "oracle_impl.h", "oracle.h", "nsdf.c", "thermal.c",
-                                              "proximity.c")]
+                                              "proximity.c", "elastomer.c")]
     srcs = [s for s in srcs if os.path.exists(s)]
     if not force and os.path.exists(_LIB) and all(os.path.getmtime(_LIB) >= os.path.getmtime(s) for s in srcs):
         return _LIB
@@ -463,3 +463,78 @@ def prox_run(link_offset, taxel_pos, taxel_normal, taxel_radius, clouds, link_st
     lib.or_prox_run(C.byref(Pb), ls.ctypes.data, oid.ctypes.data, _ptr(ost), int(step0), S, _ptr(gn),
                     ft.ctypes.data, mass.ctypes.data, _ptr(cnt), int(threads or os.cpu_count() or 1))
     return (ft, mass, cnt) if with_count else (ft, mass)
+
+
+# ---------------------------------------------------------------------------------------------
+# ElastomerTaxel (elastomer.c)
+# ---------------------------------------------------------------------------------------------
+class OrElastProblem(C.Structure):
+    _fields_ = [("num_envs", C.c_int32), ("num_links", C.c_int32), ("num_taxels", C.c_int32),
+                ("num_objects", C.c_int32), ("link_offset", C.c_void_p), ("taxel_pos", C.c_void_p),
+                ("taxel_normal", C.c_void_p), ("taxel_radius", C.c_void_p), ("num_sensor_links", C.c_int32),
+                ("sensor_links", C.c_void_p), ("pad_center", C.c_void_p), ("pad_half", C.c_void_p),
+                ("cloud_offset", C.c_void_p), ("cloud", C.c_void_p), ("s_d", C.c_double), ("s_s", C.c_double),
+                ("lambda_d", C.c_double), ("lambda_s", C.c_double), ("alpha", C.c_double), ("c", C.c_double),
+                ("eps", C.c_double), ("eta_enter", C.c_float), ("eta_exit", C.c_float), ("max_points", C.c_int32)]
+
+
+class OrElastState(C.Structure):
+    _fields_ = [("anchor", C.c_void_p), ("active", C.c_void_p), ("last_oid", C.c_void_p)]
+
+
+ELASTOMER_DEFAULTS = dict(s_d=100.0, s_s=100.0, lambda_d=8000.0, lambda_s=2000.0, alpha=1.2, c=1.0, eps=2e-3,
+                          eta_enter=1e-5, eta_exit=1e-4)
+
+
+def elastomer_new_state(num_envs, num_sensor_links, max_points):
+    return {"anchor": np.zeros((num_envs, num_sensor_links, max_points, 3), np.float32),
+            "active": np.zeros((num_envs, num_sensor_links, max_points), np.uint8),
+            "last_oid": np.full((num_envs, num_sensor_links), -2, np.int32)}
+
+
+def elastomer_run(link_offset, taxel_pos, taxel_normal, taxel_radius, sensor_links, pad_center, pad_half, clouds,
+                  link_state, obj_id, obj_state, depth, state=None, threads=0, **params):
+    """ElastomerTaxel marker displacements (App. A.7).  link_state [S][13][E*L], obj_id [S][E],
+    obj_state [S][13][E] or None, depth [S][E][T] (the readout's clean depth, float32), clouds:
+    list of [n_o][3] object-frame points.  state (elastomer_new_state(...) or None: no anchors) is
+    updated in place.  Returns (disp [S][3][E][T] link frame, absum [S][E][T], state); entries of
+    taxels outside the sensor links are 0."""
+    lib = _load()
+    if not getattr(lib, "_elast_ready", False):
+        lib.or_elast_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_int32, C.c_void_p, C.c_void_p, C.c_int]
+        lib._elast_ready = True
+    prm = dict(ELASTOMER_DEFAULTS)
+    prm.update(params)
+    off = np.ascontiguousarray(link_offset, np.int32)
+    pos = np.ascontiguousarray(taxel_pos, np.float32).reshape(-1, 3)
+    nrm = np.ascontiguousarray(taxel_normal, np.float32).reshape(-1, 3)
+    rad = np.ascontiguousarray(taxel_radius, np.float32).reshape(-1)
+    T, L = pos.shape[0], off.size - 1
+    sl = np.ascontiguousarray(sensor_links, np.int32)
+    pc = np.ascontiguousarray(pad_center, np.float32).reshape(-1, 3)
+    ph = np.ascontiguousarray(pad_half, np.float32).reshape(-1, 3)
+    coff = np.zeros(len(clouds) + 1, np.int32)
+    coff[1:] = np.cumsum([len(c) for c in clouds])
+    cloud = np.ascontiguousarray(np.concatenate([np.asarray(c, np.float32).reshape(-1, 3) for c in clouds])
+                                 if clouds else np.zeros((0, 3), np.float32))
+    NP = max([len(c) for c in clouds] + [1])
+    ls = np.ascontiguousarray(link_state, np.float32)
+    oid = np.ascontiguousarray(obj_id, np.int32)
+    S, E = oid.shape
+    assert ls.shape == (S, 13, E * L)
+    ost = None if obj_state is None else np.ascontiguousarray(obj_state, np.float32)
+    dep = np.ascontiguousarray(depth, np.float32).reshape(S, E, T)
+    if state is None:
+        state = elastomer_new_state(E, sl.size, NP)
+    assert state["anchor"].shape == (E, sl.size, NP, 3)
+    Pb = OrElastProblem(E, L, T, len(clouds), off.ctypes.data, pos.ctypes.data, nrm.ctypes.data, rad.ctypes.data,
+                        sl.size, sl.ctypes.data, pc.ctypes.data, ph.ctypes.data, coff.ctypes.data, cloud.ctypes.data,
+                        prm["s_d"], prm["s_s"], prm["lambda_d"], prm["lambda_s"], prm["alpha"], prm["c"], prm["eps"],
+                        prm["eta_enter"], prm["eta_exit"], NP)
+    St = OrElastState(state["anchor"].ctypes.data, state["active"].ctypes.data, state["last_oid"].ctypes.data)
+    disp = np.zeros((S, 3, E, T))
+    absum = np.zeros((S, E, T))
+    lib.or_elast_run(C.byref(Pb), C.byref(St), ls.ctypes.data, oid.ctypes.data, _ptr(ost), dep.ctypes.data, S,
+                     disp.ctypes.data, absum.ctypes.data, int(threads or os.cpu_count() or 1))
+    return disp, absum, state
