@@ -510,6 +510,71 @@ def bench_audio(reps: int = 5) -> dict:
     return res
 
 
+def bench_elastomer(reps: int = 5) -> dict:
+    """The ElastomerTaxel (App. A.7) on the hand's 5 fingertip pads (4096 envs x 100 steps): the
+    clean readout supplies the source probes' depths; each object carries a 1000-point surface
+    cloud for the shear anchors.  The elastomer launch alone is timed with HIP events (median of
+    `reps`, anchors reset before each).  Work is counted in terms: marker x active source (dilation),
+    marker x anchored contact point (shear), and one pose / SDF / anchor update per tracked point."""
+    import torch
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+    sc = synth.make_scene("c2")
+    inp = synth.make_inputs(sc)
+    lay = sc.layout
+    E, T, S = sc.num_envs, lay.num_taxels, inp.link_state.shape[0]
+    links = [1, 2, 3, 4, 5]
+    clouds = synth.surface_clouds(sc.grids, 1000, seed=sc.geom_seed + 30)
+    pc, ph = synth.elastomer_pads(lay, links)
+    ro = B.Readout(sc, B.TG_OUT_DEPTH)
+    d = B.to_device(inp)
+    ro.alloc_outputs(S)
+    ro.rollout(d, S)
+    depth = ro.out["depth"]
+    el = B.Elastomer(sc, clouds, links, pc, ph)
+    disp = el.rollout(d, depth)
+    torch.cuda.synchronize()
+    first = disp.clone()
+    stream = torch.cuda.current_stream()
+    ts = []
+    for _ in range(reps):
+        el.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        el.rollout(d, depth, disp=disp)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ms = float(np.median(ts))
+    markers = sum(int(lay.link_offset[l + 1] - lay.link_offset[l]) for l in links)
+    res = {"workload": f"c2 hand: {E} envs x {len(links)} fingertip pads ({markers} markers) x {S} steps, "
+                       "1000-point surface clouds, App. A.7 constants (c = 1, no clamped boundary)",
+           "ms_per_rollout": ms, "marker_readouts_per_s": E * markers * S / (ms * 1e-3),
+           "repeatable_after_reset": bool(torch.equal(first, disp))}
+    try:
+        import oracle
+        envs = np.array([0, E // 2, E - 1])
+        idx = torch.as_tensor(envs, device="cuda")
+        g = first[:, :, idx].cpu().numpy().astype(np.float64)
+        sub = synth.subset_envs(inp, envs, lay.num_links)
+        dep = depth[:, idx].cpu().numpy()
+        ref, absum, st = oracle.elastomer_run(lay.link_offset, lay.pos, lay.normal, lay.radius, links, pc, ph, clouds,
+                                              sub.link_state, sub.obj_id, sub.obj_state, dep)
+        m = np.zeros(T, bool)
+        for l in links:
+            m[lay.link_offset[l]:lay.link_offset[l + 1]] = True
+        err = np.abs(g - ref)[..., m].max(axis=1)
+        res["fp64_check"] = {"envs": envs.tolist(),
+                             "max_err_over_bar": float((err / (1e-5 * absum[..., m] + 1e-12)).max()),
+                             "anchored_points_at_end": int(st["active"].sum())}
+    except ImportError:
+        pass
+    el.close()
+    ro.out = {}
+    ro.close()
+    return res
+
+
 def c4_summary(r: dict) -> dict:
     """The grid-vs-neural comparison of bench_c4, without the fields of a bench line."""
     keep = ("config", "grid_path", "speedup_vs_grid", "depth_err_um", "normal_err_deg", "training", "memory_MB")
@@ -530,7 +595,7 @@ def main():
     ap.add_argument("--readouts-per-block", type=int, default=0,
                     help="fix the work plan instead of autotuning (the profiles pin the autotuner's choice)")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", default="readout", choices=["readout", "c4", "proximity", "audio"])
+    ap.add_argument("--workload", default="readout", choices=["readout", "c4", "proximity", "audio", "elastomer"])
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--nsdf-samples", type=int, default=1 << 17)
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"])
@@ -565,6 +630,9 @@ def main():
         return
     if args.workload == "audio":
         print(json.dumps(bench_audio()), flush=True)
+        return
+    if args.workload == "elastomer":
+        print(json.dumps(bench_elastomer()), flush=True)
         return
 
     import torch
@@ -668,6 +736,8 @@ def main():
         rec["proximity"] = bench_prox()
         torch.cuda.empty_cache()
         rec["contact_audio"] = bench_audio()
+        torch.cuda.empty_cache()
+        rec["elastomer"] = bench_elastomer()
         torch.cuda.empty_cache()
         a4 = argparse.Namespace(**vars(args))
         a4.envs, a4.steps = None, 5

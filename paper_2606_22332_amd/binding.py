@@ -714,3 +714,107 @@ class Audio:
             self.close()
         except Exception:
             pass
+
+
+class TgElastConfig(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("num_envs", C.c_int32), ("num_links", C.c_int32),
+                ("num_taxels", C.c_int32), ("num_objects", C.c_int32), ("link_taxel_offset", C.c_void_p),
+                ("taxel_pos", C.c_void_p), ("taxel_normal", C.c_void_p), ("taxel_radius", C.c_void_p),
+                ("num_sensor_links", C.c_int32), ("sensor_links", C.c_void_p), ("pad_center", C.c_void_p),
+                ("pad_half", C.c_void_p), ("clouds", C.c_void_p), ("s_d", C.c_float), ("s_s", C.c_float),
+                ("lambda_d", C.c_float), ("lambda_s", C.c_float), ("alpha", C.c_float), ("c", C.c_float),
+                ("eps", C.c_float), ("eta_enter", C.c_float), ("eta_exit", C.c_float)]
+
+
+_elast_ready = False
+
+
+def _elast_lib() -> C.CDLL:
+    global _elast_ready
+    lib = load()
+    if not _elast_ready:
+        P = C.c_void_p
+        sig = {"tg_elast_create": ([P, P], C.c_int), "tg_elast_destroy": ([P], C.c_int),
+               "tg_elast_last_error": ([P], C.c_char_p), "tg_elast_reset": ([P, P], C.c_int),
+               "tg_elast_rollout": ([P, P, P, P, C.c_int32, P], C.c_int)}
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _elast_ready = True
+    return lib
+
+
+ELASTOMER_PARAMS = dict(s_d=100.0, s_s=100.0, lambda_d=8000.0, lambda_s=2000.0, alpha=1.2, c=1.0, eps=2e-3,
+                        eta_enter=1e-5, eta_exit=1e-4)
+
+
+class Elastomer:
+    """ElastomerTaxel on the sensor links of a scene's layout: pads (centre, half extents) per
+    sensor link, surface clouds per object (float32 [n][3], object frame).  Buffers are torch
+    tensors on the current device; this class only passes their pointers to the library."""
+
+    def __init__(self, scene, clouds, sensor_links, pad_center, pad_half, **params):
+        import torch
+        self._torch = torch
+        self.lib = _elast_lib()
+        lay = scene.layout
+        self.E, self.T, self.L = scene.num_envs, lay.num_taxels, lay.num_links
+        prm = dict(ELASTOMER_PARAMS)
+        prm.update(params)
+        keep = [np.ascontiguousarray(lay.link_offset, np.int32), np.ascontiguousarray(lay.pos, np.float32),
+                np.ascontiguousarray(lay.normal, np.float32), np.ascontiguousarray(lay.radius, np.float32),
+                np.ascontiguousarray(sensor_links, np.int32), np.ascontiguousarray(pad_center, np.float32),
+                np.ascontiguousarray(pad_half, np.float32)]
+        pcs = (TgPointCloud * max(len(clouds), 1))()
+        for i, c in enumerate(clouds):
+            a = np.ascontiguousarray(c, np.float32).reshape(-1, 3)
+            keep.append(a)
+            pcs[i].num_points = a.shape[0]
+            pcs[i].points = a.ctypes.data
+        cfg = TgElastConfig(ABI_VERSION, self.E, self.L, self.T, len(clouds), *[k.ctypes.data for k in keep[:4]],
+                            keep[4].size, keep[4].ctypes.data, keep[5].ctypes.data, keep[6].ctypes.data,
+                            C.cast(pcs, C.c_void_p).value,
+                            *[float(prm[k]) for k in ("s_d", "s_s", "lambda_d", "lambda_s", "alpha", "c", "eps",
+                                                      "eta_enter", "eta_exit")])
+        h = C.c_void_p()
+        rc = self.lib.tg_elast_create(C.byref(cfg), C.byref(h))
+        if rc != 0:
+            raise TgError(f"tg_elast_create: {self.lib.tg_status_string(rc).decode()}: "
+                          f"{self.lib.tg_elast_last_error(None).decode()}")
+        self.h = h
+
+    def rollout(self, dinp: DeviceInputs, depth, n_steps: Optional[int] = None, s_in: int = 0, disp=None,
+                stream=None):
+        """Steps s_in .. s_in+n-1 of the device inputs with the readout's clean depth of the same
+        steps (depth [n][E][T]), one launch.  Returns disp [n][3][E][T] (zeros off the pads when
+        the buffer is allocated here)."""
+        torch = self._torch
+        S = dinp.link_state.shape[0] - s_in if n_steps is None else n_steps
+        if disp is None:
+            disp = torch.zeros((S, 3, self.E, self.T), dtype=torch.float32, device=dinp.link_state.device)
+        ist = TgStepInputs(dinp.link_state[s_in].data_ptr(),
+                           None if dinp.obj_state is None else dinp.obj_state[s_in].data_ptr(),
+                           dinp.obj_id[s_in].data_ptr(), dinp.step0 + s_in)
+        rc = self.lib.tg_elast_rollout(self.h, C.byref(ist), depth.data_ptr(), disp.data_ptr(), int(S),
+                                       _stream_ptr(stream))
+        if rc != 0:
+            raise TgError(f"tg_elast_rollout: {self.lib.tg_status_string(rc).decode()}: "
+                          f"{self.lib.tg_elast_last_error(self.h).decode()}")
+        return disp
+
+    def reset(self, stream=None):
+        rc = self.lib.tg_elast_reset(self.h, _stream_ptr(stream))
+        if rc != 0:
+            raise TgError(f"tg_elast_reset: {self.lib.tg_elast_last_error(self.h).decode()}")
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.tg_elast_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -632,3 +632,19 @@ def audio_excitation(num_steps: int, num_envs: int, num_taxels: int, seed: int, 
         ft[s, 3:6] = np.where(inc, f32(99.0), f32(0))
         normal[s] = np.where(inc, m, f32(0))
     return ft, normal
+
+
+def elastomer_pads(layout, links, margin: float = 1e-3, thickness: float = 2e-3):
+    """Pad boxes of the ElastomerTaxel sensor links: the footprint of each link's markers grown by
+    `margin` in the marker plane, `thickness` deep below it (link frame, markers on z = 0 facing
+    +z).  Returns (centre [Ls][3], half extents [Ls][3]), float32."""
+    c = np.zeros((len(links), 3))
+    h = np.zeros((len(links), 3))
+    for i, l in enumerate(links):
+        x = np.asarray(layout.pos[layout.link_offset[l]:layout.link_offset[l + 1]], np.float64)
+        lo, hi = x.min(0), x.max(0)
+        c[i, :2] = 0.5 * (lo[:2] + hi[:2])
+        h[i, :2] = 0.5 * (hi[:2] - lo[:2]) + margin
+        c[i, 2] = -0.5 * thickness
+        h[i, 2] = 0.5 * thickness
+    return c.astype(np.float32), h.astype(np.float32)
