@@ -9,4 +9,4 @@ in the seeded scene generator, which holds no readout arithmetic.
 from .oracle import (Oracle, build, run_readout, philox4x32_10, bf16_round, dense_xtalk, u01,  # noqa: F401
                      nsdf_num_params, nsdf_forward, nsdf_loss_grad, nsdf_adam, nsdf_targets, nsdf_dirderiv,
                      nsdf_forward_trace, prox_run, thermal_constants, thermal_voxel, thermal_stable, thermal_run,
-                     elastomer_run, elastomer_new_state, ELASTOMER_DEFAULTS)
+                     elastomer_run, elastomer_new_state, ELASTOMER_DEFAULTS, raycast_run)

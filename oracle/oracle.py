@@ -16,7 +16,7 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile the oracle (contraction off, no fast-math, OpenMP)."""
     srcs = [os.path.join(_HERE, f) for f in ("oracle.c", "oracle_impl.h", "oracle.h", "nsdf.c", "thermal.c",
-                                              "proximity.c", "elastomer.c")]
+                                              "proximity.c", "elastomer.c", "raycast.c")]
     srcs = [s for s in srcs if os.path.exists(s)]
     if not force and os.path.exists(_LIB) and all(os.path.getmtime(_LIB) >= os.path.getmtime(s) for s in srcs):
         return _LIB
@@ -538,3 +538,54 @@ def elastomer_run(link_offset, taxel_pos, taxel_normal, taxel_radius, sensor_lin
     lib.or_elast_run(C.byref(Pb), C.byref(St), ls.ctypes.data, oid.ctypes.data, _ptr(ost), dep.ctypes.data, S,
                      disp.ctypes.data, absum.ctypes.data, int(threads or os.cpu_count() or 1))
     return disp, absum, state
+
+
+# ---------------------------------------------------------------------------------------------
+# Raycast contact-depth backend (raycast.c)
+# ---------------------------------------------------------------------------------------------
+class OrRayProblem(C.Structure):
+    _fields_ = [("num_envs", C.c_int32), ("num_links", C.c_int32), ("num_taxels", C.c_int32),
+                ("num_objects", C.c_int32), ("link_offset", C.c_void_p), ("taxel_pos", C.c_void_p),
+                ("taxel_normal", C.c_void_p), ("taxel_radius", C.c_void_p), ("vert_offset", C.c_void_p),
+                ("verts", C.c_void_p), ("tri_offset", C.c_void_p), ("tris", C.c_void_p)]
+
+
+def raycast_run(link_offset, taxel_pos, taxel_normal, taxel_radius, meshes, link_state, obj_id, obj_state=None,
+                tri_query=None, threads=0):
+    """Raycast contact depth (App. A.1) by brute force over every triangle, FP64.  meshes: list of
+    (verts [n][3] f32, tris [m][3] i32) per object, outward faces.  Returns (depth [S][E][T],
+    normal [S][3][E][T] link frame, tri [S][E][T] winning triangle or -1) and, with tri_query
+    [S][E][T], a fourth value: the penetration of each queried triangle alone."""
+    lib = _load()
+    if not getattr(lib, "_ray_ready", False):
+        lib.or_ray_run.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        lib._ray_ready = True
+    off = np.ascontiguousarray(link_offset, np.int32)
+    pos = np.ascontiguousarray(taxel_pos, np.float32).reshape(-1, 3)
+    nrm = np.ascontiguousarray(taxel_normal, np.float32).reshape(-1, 3)
+    rad = np.ascontiguousarray(taxel_radius, np.float32).reshape(-1)
+    T, L = pos.shape[0], off.size - 1
+    voff = np.zeros(len(meshes) + 1, np.int32)
+    toff = np.zeros(len(meshes) + 1, np.int32)
+    voff[1:] = np.cumsum([len(m[0]) for m in meshes])
+    toff[1:] = np.cumsum([len(m[1]) for m in meshes])
+    verts = np.ascontiguousarray(np.concatenate([np.asarray(m[0], np.float32).reshape(-1, 3) for m in meshes])
+                                 if meshes else np.zeros((0, 3), np.float32))
+    tris = np.ascontiguousarray(np.concatenate([np.asarray(m[1], np.int32).reshape(-1, 3) for m in meshes])
+                                if meshes else np.zeros((0, 3), np.int32))
+    ls = np.ascontiguousarray(link_state, np.float32)
+    oid = np.ascontiguousarray(obj_id, np.int32)
+    S, E = oid.shape
+    assert ls.shape == (S, 13, E * L)
+    ost = None if obj_state is None else np.ascontiguousarray(obj_state, np.float32)
+    Pb = OrRayProblem(E, L, T, len(meshes), off.ctypes.data, pos.ctypes.data, nrm.ctypes.data, rad.ctypes.data,
+                      voff.ctypes.data, verts.ctypes.data, toff.ctypes.data, tris.ctypes.data)
+    depth = np.zeros((S, E, T))
+    normal = np.zeros((S, 3, E, T))
+    tri = np.zeros((S, E, T), np.int32)
+    tq = None if tri_query is None else np.ascontiguousarray(tri_query, np.int32).reshape(S, E, T)
+    tp = None if tri_query is None else np.zeros((S, E, T))
+    lib.or_ray_run(C.byref(Pb), ls.ctypes.data, oid.ctypes.data, _ptr(ost), S, depth.ctypes.data, normal.ctypes.data,
+                   tri.ctypes.data, _ptr(tq), _ptr(tp), int(threads or os.cpu_count() or 1))
+    return (depth, normal, tri) if tri_query is None else (depth, normal, tri, tp)

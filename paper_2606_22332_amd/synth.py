@@ -648,3 +648,107 @@ def elastomer_pads(layout, links, margin: float = 1e-3, thickness: float = 2e-3)
         c[i, 2] = -0.5 * thickness
         h[i, 2] = 0.5 * thickness
     return c.astype(np.float32), h.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------------------------
+# Triangle meshes of the objects (the raycast depth backend's collision meshes)
+# ---------------------------------------------------------------------------------------------
+def _orient_outward(v: np.ndarray, t: np.ndarray, inside: np.ndarray) -> np.ndarray:
+    """Flip triangles whose normal points toward `inside` (a point inside the solid near them is
+    given per triangle), so every face normal points out."""
+    a, b, c = v[t[:, 0]], v[t[:, 1]], v[t[:, 2]]
+    n = np.cross(b - a, c - a)
+    flip = np.sum(n * (a - inside), axis=1) < 0
+    t = t.copy()
+    t[flip] = t[flip][:, [0, 2, 1]]
+    return t
+
+
+def _grid_tris(nu: int, nv: int, wrap_v: bool) -> np.ndarray:
+    """Triangles of an nu x nv vertex grid (u wraps; v wraps if wrap_v), vertex index u * nv + v."""
+    tris = []
+    for i in range(nu):
+        i2 = (i + 1) % nu
+        for j in range(nv if wrap_v else nv - 1):
+            j2 = (j + 1) % nv
+            a, b, c, d = i * nv + j, i2 * nv + j, i2 * nv + j2, i * nv + j2
+            tris += [(a, b, c), (a, c, d)]
+    return np.array(tris, np.int32)
+
+
+def shape_mesh(s: dict, detail: int = 3):
+    """A closed, outward-oriented triangle mesh of shape `s` (object frame): (verts [n][3] f32,
+    tris [m][3] i32).  Vertices lie on the exact surface."""
+    f = s["family"]
+    if f == "sphere":
+        t0 = (1 + 5 ** 0.5) / 2
+        v = np.array([[-1, t0, 0], [1, t0, 0], [-1, -t0, 0], [1, -t0, 0], [0, -1, t0], [0, 1, t0], [0, -1, -t0],
+                      [0, 1, -t0], [t0, 0, -1], [t0, 0, 1], [-t0, 0, -1], [-t0, 0, 1]], np.float64)
+        t = np.array([[0, 11, 5], [0, 5, 1], [0, 1, 7], [0, 7, 10], [0, 10, 11], [1, 5, 9], [5, 11, 4], [11, 10, 2],
+                      [10, 7, 6], [7, 1, 8], [3, 9, 4], [3, 4, 2], [3, 2, 6], [3, 6, 8], [3, 8, 9], [4, 9, 5],
+                      [2, 4, 11], [6, 2, 10], [8, 6, 7], [9, 8, 1]], np.int64)
+        verts = [x / np.linalg.norm(x) for x in v]
+        for _ in range(detail):
+            mid = {}
+            def m(i, j):
+                k = (min(i, j), max(i, j))
+                if k not in mid:
+                    p = verts[i] + verts[j]
+                    verts.append(p / np.linalg.norm(p))
+                    mid[k] = len(verts) - 1
+                return mid[k]
+            nt = []
+            for a, b, c in t:
+                ab, bc, ca = m(a, b), m(b, c), m(c, a)
+                nt += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+            t = np.array(nt, np.int64)
+        v = np.array(verts) * s["r"]
+        t = _orient_outward(v, t.astype(np.int32), np.zeros((len(t), 3)))
+    elif f == "box":
+        b = s["b"]
+        v = np.array([[x, y, z] for x in (-1, 1) for y in (-1, 1) for z in (-1, 1)], np.float64) * b
+        t = np.array([[0, 1, 3], [0, 3, 2], [4, 6, 7], [4, 7, 5], [0, 4, 5], [0, 5, 1], [2, 3, 7], [2, 7, 6],
+                      [0, 2, 6], [0, 6, 4], [1, 5, 7], [1, 7, 3]], np.int32)
+        t = _orient_outward(v, t, np.zeros((12, 3)))
+    elif f == "capsule":
+        r, hl = s["r"], s["hl"]
+        nu, nr = 8 * (2 ** detail) // 2, 2 ** detail + 1      # around the axis; rings per hemisphere
+        rows = [(r * np.sin(th), hl + r * np.cos(th)) for th in 0.5 * np.pi * np.arange(1, nr + 1) / nr]
+        rows += [(r * np.sin(th), -hl + r * np.cos(th)) for th in 0.5 * np.pi * (1 + np.arange(0, nr) / nr)]
+        phi = 2 * np.pi * np.arange(nu) / nu
+        ring = np.array([[rr * np.cos(p), rr * np.sin(p), z] for p in phi for (rr, z) in rows])
+        nv = len(rows)
+        t = _grid_tris(nu, nv, wrap_v=False)
+        top, bot = len(ring), len(ring) + 1
+        v = np.concatenate([ring, [[0, 0, hl + r], [0, 0, -hl - r]]])
+        caps = []
+        for i in range(nu):
+            i2 = (i + 1) % nu
+            caps += [(top, i2 * nv, i * nv), (bot, i * nv + nv - 1, i2 * nv + nv - 1)]
+        t = np.concatenate([t, np.array(caps, np.int32)])
+        ctr = v[t].mean(axis=1)
+        inside = np.zeros_like(ctr)
+        inside[:, 2] = np.clip(ctr[:, 2], -hl, hl)
+        t = _orient_outward(v, t, inside)
+    elif f == "torus":
+        R, r = s["R"], s["r"]
+        nu, nv = 12 * 2 ** detail // 2, 6 * 2 ** detail // 2
+        u = 2 * np.pi * np.arange(nu) / nu
+        w = 2 * np.pi * np.arange(nv) / nv
+        v = np.array([[(R + r * np.cos(b)) * np.cos(a), (R + r * np.cos(b)) * np.sin(a), r * np.sin(b)]
+                      for a in u for b in w])
+        t = _grid_tris(nu, nv, wrap_v=True)
+        ctr = v[t].mean(axis=1)
+        ang = np.arctan2(ctr[:, 1], ctr[:, 0])
+        inside = np.stack([R * np.cos(ang), R * np.sin(ang), np.zeros(len(t))], 1)
+        t = _orient_outward(v, t, inside)
+    elif f == "hull":
+        v = np.asarray(s["verts"], np.float64)
+        t = _orient_outward(v, np.asarray(s["tris"], np.int32), np.tile(v.mean(0), (len(s["tris"]), 1)))
+    else:
+        raise ValueError(f)
+    return np.ascontiguousarray(v, np.float32), np.ascontiguousarray(t, np.int32)
+
+
+def object_meshes(grids, detail: int = 3):
+    return [shape_mesh(g.shape, detail) for g in grids]
