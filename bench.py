@@ -575,6 +575,67 @@ def bench_elastomer(reps: int = 5) -> dict:
     return res
 
 
+def bench_raycast(reps: int = 5) -> dict:
+    """The raycast contact-depth backend (App. A.1) on the hand (4096 envs x 200 taxels x 100 steps)
+    over the 8 objects' triangle meshes (icospheres, boxes, capsules, tori, convex hulls; 12 to 2304
+    triangles), one launch per rollout timed with HIP events (median of `reps`), beside the grid
+    backend's depth-only rollout of the same steps; sampled envs against the FP64 brute force."""
+    import torch
+    from paper_2606_22332_amd import binding as B
+    from paper_2606_22332_amd import synth
+    sc = synth.make_scene("c2")
+    inp = synth.make_inputs(sc)
+    E, T, S = sc.num_envs, sc.layout.num_taxels, inp.link_state.shape[0]
+    meshes = synth.object_meshes(sc.grids)
+    rc = B.Raycast(sc, meshes)
+    d = B.to_device(inp)
+    dep, nm, tri = rc.rollout(d)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    def timed(fn):
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return float(np.median(ts))
+    ms = timed(lambda: rc.rollout(d, depth=dep, normal=nm, tri=tri))
+    ro = B.Readout(sc, B.TG_OUT_DEPTH)
+    ro.set_work_plan(512)
+    ro.alloc_outputs(S)
+    ro.rollout(d, S)
+    torch.cuda.synchronize()
+    ms_grid = timed(lambda: ro.rollout(d, S))
+    gdep = ro.out["depth"]
+    both = (dep > 0) & (gdep > 0)
+    res = {"workload": f"c2 hand: {E} envs x {T} taxels x {S} steps, raycast depth over BVHs of "
+                       f"{sum(len(m[1]) for m in meshes)} triangles (8 objects)",
+           "ms_per_rollout": ms, "readouts_per_s": E * T * S / (ms * 1e-3),
+           "grid_backend_depth_only_ms": ms_grid,
+           "contact_fraction": float((dep > 0).float().mean().item()),
+           "vs_grid_depth_um": {"p50": float((dep - gdep)[both].abs().median().item() * 1e6),
+                                "p99": float(torch.quantile((dep - gdep)[both].abs()[:1 << 20].float(), 0.99).item() * 1e6)}}
+    try:
+        import oracle
+        envs = np.array([0, E // 2, E - 1])
+        idx = torch.as_tensor(envs, device="cuda")
+        sub = synth.subset_envs(inp, envs, sc.layout.num_links)
+        lay = sc.layout
+        rd, _, _ = oracle.raycast_run(lay.link_offset, lay.pos, lay.normal, lay.radius, meshes, sub.link_state,
+                                      sub.obj_id, sub.obj_state)
+        res["fp64_check"] = {"envs": envs.tolist(),
+                             "max_depth_err_um": float(np.abs(dep[:, idx].cpu().numpy() - rd).max() * 1e6)}
+    except ImportError:
+        pass
+    rc.close()
+    ro.out = {}
+    ro.close()
+    return res
+
+
 def c4_summary(r: dict) -> dict:
     """The grid-vs-neural comparison of bench_c4, without the fields of a bench line."""
     keep = ("config", "grid_path", "speedup_vs_grid", "depth_err_um", "normal_err_deg", "training", "memory_MB")
@@ -595,7 +656,7 @@ def main():
     ap.add_argument("--readouts-per-block", type=int, default=0,
                     help="fix the work plan instead of autotuning (the profiles pin the autotuner's choice)")
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--workload", default="readout", choices=["readout", "c4", "proximity", "audio", "elastomer"])
+    ap.add_argument("--workload", default="readout", choices=["readout", "c4", "proximity", "audio", "elastomer", "raycast"])
     ap.add_argument("--train-steps", type=int, default=5000)
     ap.add_argument("--nsdf-samples", type=int, default=1 << 17)
     ap.add_argument("--lr-schedule", default="constant", choices=["constant", "cosine"])
@@ -633,6 +694,9 @@ def main():
         return
     if args.workload == "elastomer":
         print(json.dumps(bench_elastomer()), flush=True)
+        return
+    if args.workload == "raycast":
+        print(json.dumps(bench_raycast()), flush=True)
         return
 
     import torch
@@ -738,6 +802,8 @@ def main():
         rec["contact_audio"] = bench_audio()
         torch.cuda.empty_cache()
         rec["elastomer"] = bench_elastomer()
+        torch.cuda.empty_cache()
+        rec["raycast"] = bench_raycast()
         torch.cuda.empty_cache()
         a4 = argparse.Namespace(**vars(args))
         a4.envs, a4.steps = None, 5

@@ -818,3 +818,97 @@ class Elastomer:
             self.close()
         except Exception:
             pass
+
+
+class TgMesh(C.Structure):
+    _fields_ = [("num_verts", C.c_int32), ("verts", C.c_void_p), ("num_tris", C.c_int32), ("tris", C.c_void_p)]
+
+
+class TgRayConfig(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("num_envs", C.c_int32), ("num_links", C.c_int32),
+                ("num_taxels", C.c_int32), ("num_objects", C.c_int32), ("link_taxel_offset", C.c_void_p),
+                ("taxel_pos", C.c_void_p), ("taxel_normal", C.c_void_p), ("taxel_radius", C.c_void_p),
+                ("meshes", C.c_void_p)]
+
+
+_ray_ready = False
+
+
+def _ray_lib() -> C.CDLL:
+    global _ray_ready
+    lib = load()
+    if not _ray_ready:
+        P = C.c_void_p
+        sig = {"tg_ray_create": ([P, P], C.c_int), "tg_ray_destroy": ([P], C.c_int),
+               "tg_ray_last_error": ([P], C.c_char_p),
+               "tg_ray_rollout": ([P, P, P, P, P, C.c_int32, P], C.c_int)}
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _ray_ready = True
+    return lib
+
+
+class Raycast:
+    """The raycast contact-depth backend over per-object triangle meshes (list of (verts [n][3]
+    f32, tris [m][3] i32), outward faces).  Buffers are torch tensors on the current device; this
+    class only passes their pointers to the library."""
+
+    def __init__(self, scene, meshes):
+        import torch
+        self._torch = torch
+        self.lib = _ray_lib()
+        lay = scene.layout
+        self.E, self.T, self.L = scene.num_envs, lay.num_taxels, lay.num_links
+        keep = [np.ascontiguousarray(lay.link_offset, np.int32), np.ascontiguousarray(lay.pos, np.float32),
+                np.ascontiguousarray(lay.normal, np.float32), np.ascontiguousarray(lay.radius, np.float32)]
+        ms = (TgMesh * max(len(meshes), 1))()
+        for i, (v, t) in enumerate(meshes):
+            va = np.ascontiguousarray(v, np.float32).reshape(-1, 3)
+            tb = np.ascontiguousarray(t, np.int32).reshape(-1, 3)
+            keep += [va, tb]
+            ms[i].num_verts, ms[i].verts, ms[i].num_tris, ms[i].tris = va.shape[0], va.ctypes.data, tb.shape[0], tb.ctypes.data
+        cfg = TgRayConfig(ABI_VERSION, self.E, self.L, self.T, len(meshes), *[k.ctypes.data for k in keep[:4]],
+                          C.cast(ms, C.c_void_p).value)
+        h = C.c_void_p()
+        rc = self.lib.tg_ray_create(C.byref(cfg), C.byref(h))
+        if rc != 0:
+            raise TgError(f"tg_ray_create: {self.lib.tg_status_string(rc).decode()}: "
+                          f"{self.lib.tg_ray_last_error(None).decode()}")
+        self.h = h
+
+    def rollout(self, dinp: DeviceInputs, n_steps: Optional[int] = None, s_in: int = 0, depth=None, normal=None,
+                tri=None, want_normal: bool = True, want_tri: bool = True, stream=None):
+        """Steps s_in .. s_in+n-1, one launch.  Returns (depth [n][E][T], normal [n][3][E][T] or None,
+        tri [n][E][T] or None)."""
+        torch = self._torch
+        S = dinp.link_state.shape[0] - s_in if n_steps is None else n_steps
+        dev = dinp.link_state.device
+        if depth is None:
+            depth = torch.empty((S, self.E, self.T), dtype=torch.float32, device=dev)
+        if normal is None and want_normal:
+            normal = torch.empty((S, 3, self.E, self.T), dtype=torch.float32, device=dev)
+        if tri is None and want_tri:
+            tri = torch.empty((S, self.E, self.T), dtype=torch.int32, device=dev)
+        ist = TgStepInputs(dinp.link_state[s_in].data_ptr(),
+                           None if dinp.obj_state is None else dinp.obj_state[s_in].data_ptr(),
+                           dinp.obj_id[s_in].data_ptr(), dinp.step0 + s_in)
+        rc = self.lib.tg_ray_rollout(self.h, C.byref(ist), depth.data_ptr(),
+                                     None if normal is None else normal.data_ptr(),
+                                     None if tri is None else tri.data_ptr(), int(S), _stream_ptr(stream))
+        if rc != 0:
+            raise TgError(f"tg_ray_rollout: {self.lib.tg_status_string(rc).decode()}: "
+                          f"{self.lib.tg_ray_last_error(self.h).decode()}")
+        return depth, normal, tri
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            self.lib.tg_ray_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -25,7 +25,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
-SOURCES = ["tg_readout.hip", "tg_nsdf.hip", "tg_proximity.hip", "tg_audio.hip", "tg_elastomer.hip"]
+SOURCES = ["tg_readout.hip", "tg_nsdf.hip", "tg_proximity.hip", "tg_audio.hip", "tg_elastomer.hip", "tg_raycast.hip"]
 
 
 def build(verbose: bool = False) -> str:
