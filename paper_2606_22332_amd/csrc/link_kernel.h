@@ -477,12 +477,21 @@ __global__ void __launch_bounds__(512, 4) tg_link_kernel(const KLaunch qarg) {
         box_muller(odd ? y2 : y0, odd ? y3 : y1, gw[4], gw[5]);
       }
       float fo[6];
+      // The two lag rates as values in SGPRs: a per-lane choice between the two fields of the
+      // constant block otherwise becomes a per-lane select of their addresses and six vector
+      // loads per step.
+      float k_load = 0.f, k_unload = 0.f;
+      if (HY == 1) {
+        k_load = p.kload;
+        k_unload = p.kunload;
+        asm volatile("" : "+s"(k_load), "+s"(k_unload));
+      }
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         const float x = zt[c];
         float h = x;
         if (HY == 1) {
-          const float kap = fabsf(x) > fabsf(Y[c]) ? p.kload : p.kunload;
+          const float kap = fabsf(x) > fabsf(Y[c]) ? k_load : k_unload;
           Y[c] = fmaf(kap, x - Y[c], Y[c]);
           h = Y[c];
         } else if (HY == 2) {
