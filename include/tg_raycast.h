@@ -15,9 +15,9 @@
  * axis to the surface), R_j - phi to leading order for faces facing the probe.
  *
  * The library builds one BVH per object at create (median splits on the longest axis of the
- * triangle centroids, at most 4 triangles per leaf).  One thread per (env, probe) traverses it
- * twice per step: a sphere query whose radius shrinks as the best penetration grows, then a
- * closest-hit ray query.  Geometry is FP32.
+ * triangle centroids, at most 4 triangles per leaf).  One thread per (step, env, probe) traverses
+ * it twice: a sphere query whose radius shrinks as the best penetration grows, then a closest-hit
+ * ray query, both nearer child first.  Geometry is FP32.
  *
  * Conventions are those of tg_readout.h: create deep-copies the host arrays; device buffers are
  * caller-owned and must stay valid until the queued work finishes; calls return a tg_status and

@@ -1,22 +1,26 @@
 // Raycast contact-depth backend (App. A.1) behind include/tg_raycast.h.
 //
 // Data: per object a BVH over its triangles, built on the host by median splits along the
-// longest axis of the triangle centroids (at most 4 triangles per leaf), flattened depth first
-// (the left child follows its parent; the right child's index is stored), node boxes grown by a
-// relative 1e-6 so FP32 rounding never culls a triangle the exact test would keep.  Triangles are
-// stored in leaf order as (a, b, c, outward unit normal), 64 B each, with the mesh's own index.
+// longest axis of the triangle centroids (at most 4 triangles per leaf), boxes grown by a
+// relative 1e-6 so FP32 rounding never culls a triangle the exact test would keep.  An interior
+// node is one 64-byte record holding its two children's entries (box, and either the child's
+// record or its leaf's first triangle and count), so one load gives both boxes and a child that
+// fails its test is never loaded; each object's root entry is kept apart.  Triangles are stored
+// in leaf order as (a, b, c, outward unit normal), 64 B each, with the mesh's own index.
 //
-// One thread per (env, probe), persistent over the steps of a launch.  Per step: the probe's
-// centre and axis in the object frame, then two traversals with a stack in LDS (one column per
-// thread, so equal stack depths fall in different banks):
-//   1. the sphere query: nodes within R - best of the centre; at a leaf the closest point of
-//      each triangle (Voronoi regions of the triangle, with the hardware reciprocal: 1 ulp);
-//      best penetration R - dist, the square root taken only for a triangle closer than the bound;
-//   2. the ray query along -a: nodes the ray enters before the nearest hit so far; at a leaf the
-//      ray-triangle test (Moller-Trumbore, barycentric slack 1e-6); if the nearest hit leaves the
-//      mesh, R + t competes with the sphere's best.  It is skipped for centres known to be
-//      outside (outside the object's box, or on the outer side of the face holding the closest
-//      point), where its first crossing could only enter the mesh.
+// One thread per (step, env, probe), a block row per step.  The probe's centre and axis in the
+// object frame, then two traversals, each descending into the nearer of
+// two passing children and parking the other on a stack in LDS (one column per thread, so equal
+// stack depths fall in different banks); leaves are tested as soon as their entry passes:
+//   1. the sphere query: children within R - best of the centre, nearer box first; at a leaf the
+//      closest point of each triangle (Voronoi regions of the triangle, with the hardware
+//      reciprocal: 1 ulp); best penetration R - dist, the square root taken only for a triangle
+//      closer than the bound;
+//   2. the ray query along -a: children the ray enters before the nearest hit so far, nearer
+//      entry first; at a leaf the ray-triangle test (Moller-Trumbore, barycentric slack 1e-6);
+//      if the nearest hit leaves the mesh, R + t competes with the sphere's best.  It is skipped
+//      for centres known to be outside (outside the object's box, or on the outer side of the
+//      face holding the closest point), where its first crossing could only enter the mesh.
 // Neighbouring lanes are neighbouring probes of one link, so their traversals visit nearly the
 // same nodes (L2 hits; the meshes are a few hundred KB).
 #include <hip/hip_runtime.h>
@@ -39,8 +43,8 @@ thread_local std::string g_ray_create_error;
 constexpr int RC_THREADS = 256;
 constexpr int RC_STACK = 32;
 
-struct RayNode {
-  float4 lo;   // box min; w: right child (interior) or first triangle (leaf), as int bits
+struct RayNode {   // a child entry: an interior record's two children are entries 2 r and 2 r + 1
+  float4 lo;   // box min; w: the child's record (interior) or its first triangle (leaf), as int bits
   float4 hi;   // box max; w: 0 (interior) or the leaf's triangle count, as int bits
 };
 struct RayTri {
@@ -54,8 +58,8 @@ struct RayParams {
   int32_t E, L, T, n_obj;
   const float4* tax_a;      // [T] (x_j, R_j)
   const float4* tax_b;      // [T] (n_j, link id as int bits)
-  const int32_t* root;      // [n_obj] root node of each object
-  const RayNode* nodes;
+  const RayNode* root;      // [n_obj] root entry of each object
+  const RayNode* nodes;     // [2 * records] child entries
   const RayTri* tris;
 };
 
@@ -142,7 +146,9 @@ __global__ __launch_bounds__(RC_THREADS) void tg_ray_kernel(const RayParams p, c
   const int l = __float_as_int(tb.w);
   const float R = ta.w;
   int32_t* st = stk + tid;
-  for (int s = 0; s < q.n_steps; ++s) {
+  // one step per block row (the steps are independent): many more waves than a loop over the
+  // steps in each thread, so the chip fills and the divergent traversals balance out
+  for (int s = blockIdx.y; s < q.n_steps; s += gridDim.y) {
     float v[7];
     const float* ls = q.link_state + (int64_t)s * 13 * EL + (int64_t)e * p.L + l;
 #pragma unroll
@@ -166,40 +172,60 @@ __global__ __launch_bounds__(RC_THREADS) void tg_ray_kernel(const RayParams p, c
       float qo[3], ao[3];
       mat_T_vec(RO, (v[0] + x[0]) - pO[0], (v[1] + x[1]) - pO[1], (v[2] + x[2]) - pO[2], qo);
       mat_T_vec(RO, a[0], a[1], a[2], ao);
-      const int root = p.root[oid];
-      const float4 root_lo = p.nodes[root].lo, root_hi = p.nodes[root].hi;
-      // 1. sphere query: nodes closer than R - best
+      const RayNode rt = p.root[oid];
+      const float4 root_lo = rt.lo, root_hi = rt.hi;
+      // 1. sphere query: children closer than R - best
       float lim = R;
       bool bface = false;
-      int sp = 1;
-      st[0] = root;
-      while (sp > 0) {
-        const int ni = st[--sp * RC_THREADS];
-        const RayNode nd = p.nodes[ni];
-        const float ex = fmaxf(fmaxf(nd.lo.x - qo[0], qo[0] - nd.hi.x), 0.f);
-        const float ey = fmaxf(fmaxf(nd.lo.y - qo[1], qo[1] - nd.hi.y), 0.f);
-        const float ez = fmaxf(fmaxf(nd.lo.z - qo[2], qo[2] - nd.hi.z), 0.f);
-        if (!(dot3f(ex, ey, ez, ex, ey, ez) < lim * lim)) continue;
-        const int w0 = __float_as_int(nd.lo.w), cnt = __float_as_int(nd.hi.w);
-        if (cnt > 0) {
-          for (int k = 0; k < cnt; ++k) {
-            const RayTri tr = p.tris[w0 + k];
-            bool face;
-            const float d2 = tri_dist2(qo[0], qo[1], qo[2], tr.a, tr.b, tr.c, face);
-            if (d2 < lim * lim) {   // (the square root only for a deeper triangle)
-              const float pen = R - sqrtf(d2);
-              if (pen > best) {
-                best = pen;
-                bt = w0 + k;
-                bface = face;
-                lim = R - best;
-              }
-            }
+      auto sphere_tri = [&](int t) {
+        const RayTri tr = p.tris[t];
+        bool face;
+        const float d2 = tri_dist2(qo[0], qo[1], qo[2], tr.a, tr.b, tr.c, face);
+        if (d2 < lim * lim) {   // (the square root only for a deeper triangle)
+          const float pen = R - sqrtf(d2);
+          if (pen > best) {
+            best = pen;
+            bt = t;
+            bface = face;
+            lim = R - best;
           }
-        } else {   // the host bounds the depth, so both children fit
-          st[sp++ * RC_THREADS] = w0;        // right
-          st[sp++ * RC_THREADS] = ni + 1;    // left, visited first
         }
+      };
+      auto sphere_leaf = [&](const RayNode& c) {
+        const int w0 = __float_as_int(c.lo.w), cnt = __float_as_int(c.hi.w);
+        for (int k = 0; k < cnt; ++k) sphere_tri(w0 + k);
+      };
+      auto box_d2 = [&](const RayNode& c) {
+        const float ex = fmaxf(fmaxf(c.lo.x - qo[0], qo[0] - c.hi.x), 0.f);
+        const float ey = fmaxf(fmaxf(c.lo.y - qo[1], qo[1] - c.hi.y), 0.f);
+        const float ez = fmaxf(fmaxf(c.lo.z - qo[2], qo[2] - c.hi.z), 0.f);
+        return dot3f(ex, ey, ez, ex, ey, ez);
+      };
+      int sp = 0;
+      int cur = -1;
+      if (box_d2(rt) < lim * lim) {
+        if (__float_as_int(rt.hi.w) > 0) sphere_leaf(rt);
+        else cur = __float_as_int(rt.lo.w);
+      }
+      while (cur >= 0) {
+        const RayNode c0 = p.nodes[2 * cur], c1 = p.nodes[2 * cur + 1];
+        const float d0 = box_d2(c0), d1 = box_d2(c1);
+        const bool sw = d1 < d0;
+        const RayNode& na = sw ? c1 : c0;
+        const RayNode& nb = sw ? c0 : c1;
+        const float da = sw ? d1 : d0, db = sw ? d0 : d1;
+        int next = -1;
+        if (da < lim * lim) {
+          if (__float_as_int(na.hi.w) > 0) sphere_leaf(na);
+          else next = __float_as_int(na.lo.w);
+        }
+        if (db < lim * lim) {   // (lim may have shrunk at the first child's leaf)
+          if (__float_as_int(nb.hi.w) > 0) sphere_leaf(nb);
+          else if (next < 0) next = __float_as_int(nb.lo.w);
+          else st[sp++ * RC_THREADS] = __float_as_int(nb.lo.w);   // the host bounds the depth
+        }
+        if (next < 0 && sp > 0) next = st[--sp * RC_THREADS];
+        cur = next;
       }
       // 2. ray query along -a: the nearest crossing.  It can only count when the centre is inside
       //    the mesh, so it is skipped when the centre is outside the object's box, or when its
@@ -216,31 +242,52 @@ __global__ __launch_bounds__(RC_THREADS) void tg_ray_kernel(const RayParams p, c
       const float ix = 1.0f / dx, iy = 1.0f / dy, iz = 1.0f / dz;
       float tmin = INFINITY;
       int th = -1;
-      sp = outside ? 0 : 1;
-      st[0] = root;
-      while (sp > 0) {
-        const int ni = st[--sp * RC_THREADS];
-        const RayNode nd = p.nodes[ni];
-        const float t1x = (nd.lo.x - qo[0]) * ix, t2x = (nd.hi.x - qo[0]) * ix;
-        const float t1y = (nd.lo.y - qo[1]) * iy, t2y = (nd.hi.y - qo[1]) * iy;
-        const float t1z = (nd.lo.z - qo[2]) * iz, t2z = (nd.hi.z - qo[2]) * iz;
+      auto ray_tri = [&](int k) {
+        const RayTri tr = p.tris[k];
+        const float t = tri_ray(qo[0], qo[1], qo[2], dx, dy, dz, tr.a, tr.b, tr.c);
+        if (t < tmin) {
+          tmin = t;
+          th = k;
+        }
+      };
+      auto ray_leaf = [&](const RayNode& c) {
+        const int w0 = __float_as_int(c.lo.w), cnt = __float_as_int(c.hi.w);
+        for (int k = 0; k < cnt; ++k) ray_tri(w0 + k);
+      };
+      // entry parameter of the ray into a box, or +inf when it misses it before tmin
+      auto box_t = [&](const RayNode& c) {
+        const float t1x = (c.lo.x - qo[0]) * ix, t2x = (c.hi.x - qo[0]) * ix;
+        const float t1y = (c.lo.y - qo[1]) * iy, t2y = (c.hi.y - qo[1]) * iy;
+        const float t1z = (c.lo.z - qo[2]) * iz, t2z = (c.hi.z - qo[2]) * iz;
         const float tn = fmaxf(fmaxf(fminf(t1x, t2x), fminf(t1y, t2y)), fmaxf(fminf(t1z, t2z), 0.f));
         const float tf = fminf(fminf(fmaxf(t1x, t2x), fmaxf(t1y, t2y)), fminf(fmaxf(t1z, t2z), tmin));
-        if (!(tn <= tf)) continue;
-        const int w0 = __float_as_int(nd.lo.w), cnt = __float_as_int(nd.hi.w);
-        if (cnt > 0) {
-          for (int k = 0; k < cnt; ++k) {
-            const RayTri tr = p.tris[w0 + k];
-            const float t = tri_ray(qo[0], qo[1], qo[2], dx, dy, dz, tr.a, tr.b, tr.c);
-            if (t < tmin) {
-              tmin = t;
-              th = w0 + k;
-            }
-          }
-        } else {
-          st[sp++ * RC_THREADS] = w0;
-          st[sp++ * RC_THREADS] = ni + 1;
+        return tn <= tf ? tn : INFINITY;
+      };
+      sp = 0;
+      cur = -1;
+      if (!outside && box_t(rt) < INFINITY) {
+        if (__float_as_int(rt.hi.w) > 0) ray_leaf(rt);
+        else cur = __float_as_int(rt.lo.w);
+      }
+      while (cur >= 0) {
+        const RayNode c0 = p.nodes[2 * cur], c1 = p.nodes[2 * cur + 1];
+        const float t0 = box_t(c0), t1 = box_t(c1);
+        const bool sw = t1 < t0;
+        const RayNode& na = sw ? c1 : c0;
+        const RayNode& nb = sw ? c0 : c1;
+        const float ta_ = sw ? t1 : t0;
+        int next = -1;
+        if (ta_ < INFINITY) {
+          if (__float_as_int(na.hi.w) > 0) ray_leaf(na);
+          else next = __float_as_int(na.lo.w);
         }
+        if (box_t(nb) < INFINITY) {   // (re-tested: tmin may have shrunk at the first child's leaf)
+          if (__float_as_int(nb.hi.w) > 0) ray_leaf(nb);
+          else if (next < 0) next = __float_as_int(nb.lo.w);
+          else st[sp++ * RC_THREADS] = __float_as_int(nb.lo.w);
+        }
+        if (next < 0 && sp > 0) next = st[--sp * RC_THREADS];
+        cur = next;
       }
       if (th >= 0) {
         const float4 n = p.tris[th].n;
@@ -314,10 +361,11 @@ struct Builder {
           hi[k] = std::max(hi[k], x);
         }
   }
-  int build(int b, int e, int depth) {
+  // Returns the entry of the subtree over idx[b, e): its box and either its record (appended to
+  // nodes as two child entries) or its leaf's triangles (appended to tris).
+  RayNode build(int b, int e, int depth) {
     max_depth = std::max(max_depth, depth);
-    const int me = (int)nodes->size();
-    nodes->push_back(RayNode{});
+    RayNode me;
     double lo[3], hi[3];
     box(b, e, lo, hi);
     float flo[3], fhi[3];
@@ -346,8 +394,8 @@ struct Builder {
         tr.n = make_float4((float)(n[0] / ln), (float)(n[1] / ln), (float)(n[2] / ln), 0.f);
         tris->push_back(tr);
       }
-      (*nodes)[me].lo = make_float4(flo[0], flo[1], flo[2], ibits(first));
-      (*nodes)[me].hi = make_float4(fhi[0], fhi[1], fhi[2], ibits(e - b));
+      me.lo = make_float4(flo[0], flo[1], flo[2], ibits(first));
+      me.hi = make_float4(fhi[0], fhi[1], fhi[2], ibits(e - b));
       return me;
     }
     double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -363,10 +411,15 @@ struct Builder {
     std::nth_element(idx.begin() + b, idx.begin() + mid, idx.begin() + e, [&](int u, int w) {
       return cen[3 * u + ax] < cen[3 * w + ax] || (cen[3 * u + ax] == cen[3 * w + ax] && u < w);
     });
-    build(b, mid, depth + 1);
-    const int right = build(mid, e, depth + 1);
-    (*nodes)[me].lo = make_float4(flo[0], flo[1], flo[2], ibits(right));
-    (*nodes)[me].hi = make_float4(fhi[0], fhi[1], fhi[2], ibits(0));
+    const int rec = (int)(nodes->size() / 2);
+    nodes->push_back(RayNode{});
+    nodes->push_back(RayNode{});
+    const RayNode left = build(b, mid, depth + 1);
+    const RayNode right = build(mid, e, depth + 1);
+    (*nodes)[2 * (size_t)rec] = left;
+    (*nodes)[2 * (size_t)rec + 1] = right;
+    me.lo = make_float4(flo[0], flo[1], flo[2], ibits(rec));
+    me.hi = make_float4(fhi[0], fhi[1], fhi[2], ibits(0));
     return me;
   }
 };
@@ -399,7 +452,7 @@ tg_status tg_ray_create(const tg_ray_config* cfg, tg_ray** out) {
   }
   std::vector<RayNode> nodes;
   std::vector<RayTri> tris;
-  std::vector<int32_t> roots(NO);
+  std::vector<RayNode> roots(NO);
   for (int o = 0; o < NO; ++o) {
     const tg_mesh& m = cfg->meshes[o];
     if (m.num_verts < 3 || m.num_tris < 1 || !m.verts || !m.tris)
@@ -436,7 +489,7 @@ tg_status tg_ray_create(const tg_ray_config* cfg, tg_ray** out) {
   RayParams& p = h->p;
   p.E = E; p.L = L; p.T = T; p.n_obj = NO;
   float4 *dta = nullptr, *dtb = nullptr;
-  int32_t* droot = nullptr;
+  RayNode* droot = nullptr;
   RayNode* dn = nullptr;
   RayTri* dt = nullptr;
   hipError_t e = ralloc(h, &dta, T);
@@ -446,8 +499,9 @@ tg_status tg_ray_create(const tg_ray_config* cfg, tg_ray** out) {
   if (e == hipSuccess) e = ralloc(h, &dt, tris.size());
   if (e == hipSuccess) e = hipMemcpy(dta, ta.data(), T * sizeof(float4), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dtb, tb.data(), T * sizeof(float4), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(droot, roots.data(), NO * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemcpy(dn, nodes.data(), nodes.size() * sizeof(RayNode), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(droot, roots.data(), NO * sizeof(RayNode), hipMemcpyHostToDevice);
+  if (e == hipSuccess && !nodes.empty())
+    e = hipMemcpy(dn, nodes.data(), nodes.size() * sizeof(RayNode), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dt, tris.data(), tris.size() * sizeof(RayTri), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     tg_ray_destroy(h);
@@ -478,7 +532,7 @@ tg_status tg_ray_rollout(tg_ray* h, const tg_step_inputs* in, float* depth, floa
   q.tri = tri;
   q.n_steps = n_steps;
   const int64_t ET = (int64_t)h->p.E * h->p.T;
-  hipLaunchKernelGGL(tg_ray_kernel, dim3((unsigned)((ET + RC_THREADS - 1) / RC_THREADS)), dim3(RC_THREADS), 0,
+  hipLaunchKernelGGL(tg_ray_kernel, dim3((unsigned)((ET + RC_THREADS - 1) / RC_THREADS), (unsigned)std::min(n_steps, 65535)), dim3(RC_THREADS), 0,
                      (hipStream_t)hip_stream, h->p, q);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? TG_OK : rfail(h, TG_ERR_HIP, hipGetErrorString(e));
