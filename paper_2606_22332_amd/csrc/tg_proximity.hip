@@ -13,7 +13,7 @@
 // each row the sphere's chord fixes the x-range of cells, one contiguous range of points.  Against
 // cells as large as the radius (3 x 3 x 3 around the probe) this halves the points visited on the
 // hand's workload (about 775 instead of 1450 per probe, 378 of them inside the sphere).  One thread
-// per (env, taxel) runs every step of the launch; neighbouring lanes hold neighbouring taxels of
+// per (step, env, taxel), a block row per step; neighbouring lanes hold neighbouring taxels of
 // one link, so they walk nearly the same cells and their point loads hit the same L2 lines.  The
 // visits are plain FP32 ALU work (a distance, a compare, the hardware square root and four
 // multiply-adds per point inside the sphere).
@@ -75,7 +75,9 @@ __global__ __launch_bounds__(PX_THREADS) void tg_prox_kernel(const ProxParams p,
   const float4 ta = p.tax_a[j], tb = p.tax_b[j];
   const int l = __float_as_int(tb.w);
   const float g = q.gain ? q.gain[idx] : 1.0f;
-  for (int s = 0; s < q.n_steps; ++s) {
+  // one step per block row (the steps are independent): the launch has n_steps times the waves of
+  // a loop over the steps in each thread, so the chip fills and the divergent loops balance out
+  for (int s = blockIdx.y; s < q.n_steps; s += gridDim.y) {
     float v[13];
     const float* ls = q.link_state + (int64_t)s * 13 * EL + (int64_t)e * p.L + l;
 #pragma unroll
@@ -356,7 +358,8 @@ tg_status tg_prox_rollout(tg_prox* h, const tg_step_inputs* in, float* ft, float
   q.step0 = in->step;
   q.n_steps = n_steps;
   const int64_t ET = (int64_t)h->p.E * h->p.T;
-  hipLaunchKernelGGL(tg_prox_kernel, dim3((unsigned)((ET + PX_THREADS - 1) / PX_THREADS)), dim3(PX_THREADS), 0,
+  hipLaunchKernelGGL(tg_prox_kernel, dim3((unsigned)((ET + PX_THREADS - 1) / PX_THREADS), (unsigned)std::min(n_steps, 65535)),
+                     dim3(PX_THREADS), 0,
                      (hipStream_t)hip_stream, h->p, q);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? TG_OK : pfail(h, TG_ERR_HIP, hipGetErrorString(e));
