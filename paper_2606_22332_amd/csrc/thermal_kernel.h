@@ -52,67 +52,95 @@ struct ThermalLaunch {
 // The paper's spectral diffusion step (App. D.1) on a block held as z-columns `col` (thread (x,y)).
 // The mirror-padded FFT filter 1 / (1 + a k^2) is diagonal in the DCT-II basis C of the block, with
 // k^2 = (pi / (n dx))^2 (mx^2 + my^2 + mz^2).  It is applied in the equal correction form
-//   T' = T - C3^T (h * C3 T),   h = a k^2 / (1 + a k^2) <= a k_max^2,
-// so the FP32 rounding of the transforms multiplies only the small correction.  C3 is separable,
-// and each axis is a 16 x 16 matrix times a 16 x 256 matrix: FP32 MFMA 16x16x4, 64 per axis and
-// block, 16 per wave.  The block sits in the exchange buffer ex[z][y][x] (rows padded to 17 floats,
-// planes 272): a contraction reads its B operand (4 rows of the contracted axis by 16 columns)
-// straight from it and writes its 16 x 16 result back in place, each wave owning 4 whole tiles, so
-// only the change of axis needs a barrier.  The forward x transform's result feeds the inverse x
-// transform from registers: its 4 output rows per lane group are the inverse's K slices when the
-// inverse contracts mx in the order (4 g + r) over (register r, lane group g).
-//   lane l = 16 g + c:  A[i = c][k = g],  B[k = g][j = c],  D[i = 4 g + r][j = c] (register r)
-struct DctOperands {   // A operands of the DCT-II matrix C (forward) and C^T (inverse), per lane
-  float fwd[4];        // C[c][4 kb + g]       (K slice kb: k = 4 kb + g)
-  float inv[4];        // C^T[c][4 kb + g]
-  float inv_chain[4];  // C^T[c][4 g + r]      (K slice r: k = 4 g + r)
+//   T' = T - C3^T (h * C3 (T - T0)),   h = a k^2 / (1 + a k^2) <= a k_max^2,
+// so the rounding of the transforms multiplies only the small correction; T0 (the ambient
+// temperature) changes nothing in exact arithmetic (C3 maps a constant to the mean mode alone, and
+// h = 0 there) but keeps the transformed values small.  C3 is separable, and each axis is a 16 x 16
+// matrix times a 16 x 256 matrix.  Each contraction runs on FP16 MFMA with both operands split into
+// FP16 high and low parts (x = hi + lo, lo the FP16 rounding of x - hi, so hi + lo holds about 22
+// bits): one v_mfma_f32_16x16x32_f16 takes [A_hi, A_hi] times [B_hi; B_lo] and a second takes
+// [A_lo, A_lo] times the same B, so all four partial products accumulate in FP32, at a quarter of
+// the matrix-core time of FP32 MFMA 16x16x4.  The block sits in the exchange buffer ex[z][y][x]
+// (rows padded to 17 floats, planes 272): a contraction reads its B operand (the 16 values of the
+// contracted axis for one column, 4 per lane group) straight from it and writes its 16 x 16 result
+// back in place, each wave owning 4 whole tiles, so only the change of axis needs a barrier.  The
+// forward x transform's result feeds the inverse x transform from registers: its 4 output rows per
+// lane group are the inverse's K slice of that lane group.
+//   lane l = 16 g + c:  A[i = c][k = 4 g + r],  B[k = 4 g + r][j = c],  D[i = 4 g + r][j = c]
+// (register r; in the K = 32 operands slot r holds the high part of k = 4 g + r, slot 4 + r the
+// low part of B, or a second copy of A's part).
+typedef _Float16 dct_h8 __attribute__((ext_vector_type(8)));
+typedef float dct_acc __attribute__((ext_vector_type(4)));
+struct DctSplit {      // one lane's A operand of a 16 x 16 matrix: high and low FP16 parts
+  dct_h8 hi, lo;
 };
-__device__ __forceinline__ DctOperands dct_operands(const float* dct, int lane) {
-  const int g = lane >> 4, c = lane & 15;
-  DctOperands o;
+struct DctOperands {   // the DCT-II matrix C (forward) and C^T (inverse)
+  DctSplit fwd;        // C[c][4 g + r]
+  DctSplit inv;        // C^T[c][4 g + r] = C[4 g + r][c]
+};
+__device__ __forceinline__ DctSplit dct_split(const float v[4]) {
+  DctSplit o;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    o.fwd[k] = dct[c * TH_N + 4 * k + g];
-    o.inv[k] = dct[(4 * k + g) * TH_N + c];
-    o.inv_chain[k] = dct[(4 * g + k) * TH_N + c];
+  for (int r = 0; r < 4; ++r) {
+    const _Float16 h = (_Float16)v[r];
+    const _Float16 lo = (_Float16)(v[r] - (float)h);
+    o.hi[r] = h; o.hi[4 + r] = h;
+    o.lo[r] = lo; o.lo[4 + r] = lo;
   }
   return o;
 }
-typedef float dct_acc __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ dct_acc mfma4(float a, float b, dct_acc acc) {
-  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+__device__ __forceinline__ DctOperands dct_operands(const float* dct, int lane) {
+  const int g = lane >> 4, c = lane & 15;
+  float f[4], v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    f[r] = dct[c * TH_N + 4 * g + r];
+    v[r] = dct[(4 * g + r) * TH_N + c];
+  }
+  DctOperands o;
+  o.fwd = dct_split(f);
+  o.inv = dct_split(v);
+  return o;
 }
-// One axis of a wave's 4 tiles: tile t reads B slice kb at ex[base(t) + (4 kb + g) * ks + c * cs]
-// and writes D row 4 g + r at ex[base(t) + (4 g + r) * ks + c * cs] (ks: stride of the contracted
-// axis, cs: of the column axis).
-__device__ __forceinline__ void dct_axis(float* ex, const float A[4], int base0, int tstride, int ks, int cs,
+// D += A B for this lane's B values b[r] = B[4 g + r][c]
+__device__ __forceinline__ dct_acc mfma_split(const DctSplit& A, const float b[4], dct_acc acc) {
+  dct_h8 B;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const _Float16 h = (_Float16)b[r];
+    B[r] = h;
+    B[4 + r] = (_Float16)(b[r] - (float)h);
+  }
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(A.hi, B, acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(A.lo, B, acc, 0, 0, 0);
+}
+// One axis of a wave's 4 tiles: tile t reads B row k at ex[base(t) + k * ks + c * cs] and writes
+// D row 4 g + r at ex[base(t) + (4 g + r) * ks + c * cs] (ks: stride of the contracted axis, cs:
+// of the column axis).
+__device__ __forceinline__ void dct_axis(float* ex, const DctSplit& A, int base0, int tstride, int ks, int cs,
                                          int lane) {
   const int g = lane >> 4, c = lane & 15;
-  dct_acc d[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const float* src = ex + base0 + t * tstride + c * cs;
-    dct_acc acc = {0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < 4; ++t) {   // (a tile's result goes back as soon as the MFMAs have read it)
+    float* src = ex + base0 + t * tstride + c * cs;
+    float b[4];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) acc = mfma4(A[kb], src[(4 * kb + g) * ks], acc);
-    d[t] = acc;
-  }
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    float* dst = ex + base0 + t * tstride + c * cs;
-    dst[(4 * g + 0) * ks] = d[t].x;
-    dst[(4 * g + 1) * ks] = d[t].y;
-    dst[(4 * g + 2) * ks] = d[t].z;
-    dst[(4 * g + 3) * ks] = d[t].w;
+    for (int r = 0; r < 4; ++r) b[r] = src[(4 * g + r) * ks];
+    const dct_acc z = {0.f, 0.f, 0.f, 0.f};
+    const dct_acc d = mfma_split(A, b, z);
+    src[(4 * g + 0) * ks] = d.x;
+    src[(4 * g + 1) * ks] = d.y;
+    src[(4 * g + 2) * ks] = d.z;
+    src[(4 * g + 3) * ks] = d.w;
   }
 }
-__device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const float* hk, float col[TH_N], float* ex,
-                                                 int tid) {
+__device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const float* hk, float T0, float col[TH_N],
+                                                 float* ex, int tid) {
   constexpr int n = TH_N, RS = TH_N + 1, PS = TH_N * (TH_N + 1);
   const int x = tid % n, y = tid / n;
   const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
 #pragma unroll
-  for (int z = 0; z < n; ++z) ex[z * PS + y * RS + x] = col[z];
+  for (int z = 0; z < n; ++z) ex[z * PS + y * RS + x] = col[z] - T0;
   __syncthreads();
   // forward z: tiles y = 4 w + t; K = z (plane stride), columns x
   dct_axis(ex, C.fwd, 4 * w * RS, RS, PS, 1, lane);
@@ -125,16 +153,19 @@ __device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const flo
   for (int t = 0; t < 4; ++t) {
     const int mz = 4 * w + t;
     float* pl = ex + mz * PS;
-    dct_acc acc = {0.f, 0.f, 0.f, 0.f};
+    float b[4];
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) acc = mfma4(C.fwd[kb], pl[c * RS + 4 * kb + g], acc);
-    // acc: row mx = 4 g + r, column my = c
+    for (int r = 0; r < 4; ++r) b[r] = pl[c * RS + 4 * g + r];
+    const dct_acc z = {0.f, 0.f, 0.f, 0.f};
+    const dct_acc acc = mfma_split(C.fwd, b, z);
+    // acc: row mx = 4 g + r, column my = c: scaled, it is the inverse's B slice of this lane group
     const int b2 = c * c + mz * mz;
-    dct_acc inv = {0.f, 0.f, 0.f, 0.f};
-    inv = mfma4(C.inv_chain[0], acc.x * hk[(4 * g + 0) * (4 * g + 0) + b2], inv);
-    inv = mfma4(C.inv_chain[1], acc.y * hk[(4 * g + 1) * (4 * g + 1) + b2], inv);
-    inv = mfma4(C.inv_chain[2], acc.z * hk[(4 * g + 2) * (4 * g + 2) + b2], inv);
-    inv = mfma4(C.inv_chain[3], acc.w * hk[(4 * g + 3) * (4 * g + 3) + b2], inv);
+    float hb[4];
+    hb[0] = acc.x * hk[(4 * g + 0) * (4 * g + 0) + b2];
+    hb[1] = acc.y * hk[(4 * g + 1) * (4 * g + 1) + b2];
+    hb[2] = acc.z * hk[(4 * g + 2) * (4 * g + 2) + b2];
+    hb[3] = acc.w * hk[(4 * g + 3) * (4 * g + 3) + b2];
+    const dct_acc inv = mfma_split(C.inv, hb, z);
     // inv: row x = 4 g + r, column my = c (every read of the plane is behind it)
     pl[c * RS + 4 * g + 0] = inv.x;
     pl[c * RS + 4 * g + 1] = inv.y;
@@ -153,10 +184,11 @@ __device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const flo
   __syncthreads();   // the exchange buffer is free again
 }
 
-// SPEC = 1: the paper's step (spectral diffusion, T^4 radiation and convection, sensor lag); its
-// transforms want more registers than the explicit step, so it runs at two waves per SIMD.
+// SPEC = 1: the paper's step (spectral diffusion, T^4 radiation and convection, sensor lag).  Both
+// forms run at four waves per SIMD; the spectral one then spills some registers to scratch, which
+// still beats two waves per SIMD without spills by a fifth.
 template <int SPEC>
-__global__ __launch_bounds__(TH_THREADS, SPEC ? 2 : 4) void tg_thermal_kernel(const ThermalLaunch q) {
+__global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const ThermalLaunch q) {
   constexpr int n = TH_N;
   const KParams& p = *q.kc;
   const ThermalParams& th = *q.th;
@@ -223,7 +255,7 @@ __global__ __launch_bounds__(TH_THREADS, SPEC ? 2 : 4) void tg_thermal_kernel(co
       quat_to_R(os[3 * E + e], os[4 * E + e], os[5 * E + e], os[6 * E + e], op.R);
     }
     if (spec) {
-      spectral_diffuse(dcto, hks, col, ex, tid);
+      spectral_diffuse(dcto, hks, Tamb, col, ex, tid);
     } else {
 #pragma unroll
       for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];
