@@ -430,7 +430,7 @@ def bench_prox(reps: int = 5) -> dict:
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
-def bench_audio(reps: int = 5) -> dict:
+def bench_audio(reps: int = 5, lanes_per_pair: int = 0) -> dict:
     """The contact-audio sensor (App. E) on the hand's 5 fingertip links (4096 envs): the clean
     100-step readout of the 4096-env x 200-taxel hand supplies taxel forces and contact normals;
     each (env, fingertip) synthesises K = 240 samples per 5 ms step (48 kHz) through a 16-mode
@@ -454,7 +454,8 @@ def bench_audio(reps: int = 5) -> dict:
     mats = synth.audio_materials(16, K / sc.dt)
     material = (np.asarray(inp.obj_id[0]) % 3).astype(np.int32)
     dmat = torch.from_numpy(material).cuda()
-    au = B.Audio(E, T, ranges, mats, 16, K, sc.dt, g_imp=1.0, g_scr=1.0, seed=sc.noise.seed)
+    au = B.Audio(E, T, ranges, mats, 16, K, sc.dt, g_imp=1.0, g_scr=1.0, seed=sc.noise.seed,
+                 lanes_per_pair=lanes_per_pair)
     stream = torch.cuda.current_stream()
     out = au.rollout(ft, nm, dmat)
     torch.cuda.synchronize()

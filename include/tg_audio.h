@@ -61,7 +61,7 @@ typedef struct {
   double dt;                          /* physics step [s], > 0 */
   double g_imp, g_scr;                /* impact and scrape gains, finite */
   uint64_t seed;                      /* Philox key of the scrape noise */
-  int32_t lanes_per_pair;             /* lanes sharing one (env, link) bank: 1, 2 or 4, or 0 =
+  int32_t lanes_per_pair;             /* lanes sharing one (env, link) bank: 1, 2, 4, 8 or 16, or 0 =
                                          chosen at create (the smallest giving every SIMD two
                                          waves, else the largest whose block fits in LDS) */
 } tg_audio_config;

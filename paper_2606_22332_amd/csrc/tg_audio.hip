@@ -63,11 +63,19 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
+// the value of lane sub ^ 4 (rows of 16 lanes): row_shl:4 for the lower half of each group of 8,
+// row_shr:4 for the upper half
+__device__ __forceinline__ double xor4_d(double v, int sub) {
+  const double up = dpp_d<0x104>(v), down = dpp_d<0x114>(v);
+  return (sub & 4) ? down : up;
+}
 // sum over the G lanes of a pair (aligned groups of G lanes), the same in each of them
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-  if (G >= 2) v = v + dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
-  if (G >= 4) v = v + dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (G >= 2) v = v + dpp_d<0xB1>(v);    // quad_perm [1,0,3,2]
+  if (G >= 4) v = v + dpp_d<0x4E>(v);    // quad_perm [2,3,0,1]
+  if (G >= 8) v = v + dpp_d<0x141>(v);   // row_half_mirror: a lane of the other quad (all hold its sum)
+  if (G >= 16) v = v + dpp_d<0x140>(v);  // row_mirror: a lane of the other group of 8
   return v;
 }
 
@@ -88,15 +96,38 @@ __device__ __forceinline__ double bank_part(double u, const double* a1, const do
 }
 // G samples' parts p[0..G) in each lane of a pair -> lane sub gets the pair's s[k0 + sub]: a
 // transposed reduction, each exchange sending half of what the lane still holds.
+// Stage with bit `bit` of the partner: of the n values q[] (samples indexed by the bits not yet
+// reduced), keep the half whose bit matches the lane's and add the partner's copy of it.
+template <int N, int BIT>
+__device__ __forceinline__ void transpose_stage(double* q, int sub) {
+  const bool b = (sub & BIT) != 0;
+#pragma unroll
+  for (int i = 0; i < N / 2; ++i) {
+    const double keep = b ? q[2 * i + 1] : q[2 * i], send = b ? q[2 * i] : q[2 * i + 1];
+    double other;
+    if constexpr (BIT == 1) other = dpp_d<0xB1>(send);        // quad_perm [1,0,3,2]
+    else if constexpr (BIT == 2) other = dpp_d<0x4E>(send);   // quad_perm [2,3,0,1]
+    else if constexpr (BIT == 4) other = xor4_d(send, sub);
+    else other = dpp_d<0x128>(send);                          // row_ror:8 (lane sub ^ 8)
+    q[i] = keep + other;
+  }
+}
 template <int G>
 __device__ __forceinline__ double group_transpose_sum(const double* p, int sub) {
-  if (G == 1) return p[0];
-  const bool b = (sub & 1) != 0;
-  if (G == 2) return (b ? p[1] : p[0]) + dpp_d<0xB1>(b ? p[0] : p[1]);
-  const double A = (b ? p[1] : p[0]) + dpp_d<0xB1>(b ? p[0] : p[1]);   // sample b, lanes {sub, sub ^ 1}
-  const double Bv = (b ? p[3] : p[2]) + dpp_d<0xB1>(b ? p[2] : p[3]);  // sample 2 + b
-  const bool c = (sub & 2) != 0;
-  return (c ? Bv : A) + dpp_d<0x4E>(c ? A : Bv);                        // sample 2 c + b = sub
+  if constexpr (G == 1) {
+    return p[0];
+  } else {
+    double q[G];
+#pragma unroll
+    for (int i = 0; i < G; ++i) q[i] = p[i];
+    // after the stage of bit 2^j, q[i] holds sample (i << (j + 1)) | (sub & (2^(j+1) - 1)), summed
+    // over the lanes that agree with sub above bit j
+    transpose_stage<G, 1>(q, sub);
+    if constexpr (G >= 4) transpose_stage<G / 2, 2>(q, sub);
+    if constexpr (G >= 8) transpose_stage<G / 4, 4>(q, sub);
+    if constexpr (G >= 16) transpose_stage<G / 8, 8>(q, sub);
+    return q[0];
+  }
 }
 }  // namespace
 
@@ -253,6 +284,11 @@ const void* kernel_of(int G, int mpl) {
     case 66: return (const void*)tg_audio_kernel<4, 2>;
     case 68: return (const void*)tg_audio_kernel<4, 4>;
     case 72: return (const void*)tg_audio_kernel<4, 8>;
+    case 129: return (const void*)tg_audio_kernel<8, 1>;
+    case 130: return (const void*)tg_audio_kernel<8, 2>;
+    case 132: return (const void*)tg_audio_kernel<8, 4>;
+    case 257: return (const void*)tg_audio_kernel<16, 1>;
+    case 258: return (const void*)tg_audio_kernel<16, 2>;
     default: return nullptr;
   }
 }
@@ -295,8 +331,9 @@ tg_status tg_audio_create(const tg_audio_config* cfg, tg_audio** out) {
   // lanes per pair G and slots per lane MPL (powers of two, G * MPL >= slots): the smallest G
   // that gives every SIMD two waves, else the largest that fits.  The recurrence is a chain of
   // dependent FMAs per slot and the noise comes from LDS; with one wave per SIMD their latency
-  // shows (on the hand, 20480 pairs with 16 slots: 3.7 ms per 100-step launch at G = 2, 640
-  // waves, against 3.0 ms at G = 4, 1280 waves).
+  // shows, and more lanes per pair cost more exchanges per sample (on the hand, 20480 pairs with
+  // 16 slots, per 100-step launch: 3.7 ms at G = 2, 3.0 ms at G = 4, 2.9 ms at G = 8 with 2560
+  // waves, 3.3 ms at G = 16).
   const int KP = ((K + 3) & ~3) + 1;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
@@ -305,9 +342,10 @@ tg_status tg_audio_create(const tg_audio_config* cfg, tg_audio** out) {
   const int64_t nsimd = 4 * (int64_t)cus, EL = (int64_t)E * Ls;
   int G = 0, mpl = 0;
   bool done = false;
-  if (cfg->lanes_per_pair != 0 && cfg->lanes_per_pair != 1 && cfg->lanes_per_pair != 2 && cfg->lanes_per_pair != 4)
-    return afail(nullptr, TG_ERR_INVALID_ARGUMENT, "lanes_per_pair must be 0, 1, 2 or 4");
-  for (int gl = 1; gl <= 4; gl *= 2) {
+  const int lp = cfg->lanes_per_pair;
+  if (lp != 0 && lp != 1 && lp != 2 && lp != 4 && lp != 8 && lp != 16)
+    return afail(nullptr, TG_ERR_INVALID_ARGUMENT, "lanes_per_pair must be 0, 1, 2, 4, 8 or 16");
+  for (int gl = 1; gl <= 16; gl *= 2) {
     if (cfg->lanes_per_pair != 0 && gl != cfg->lanes_per_pair) continue;
     int mp = 1;
     while (mp * gl < cfg->slots) mp *= 2;

@@ -79,7 +79,7 @@ def check(g, ref):
 RANGES = [(0, 7), (7, 19), (25, 30)]       # ragged sensor links of a 30-taxel layout (19..25 unused)
 
 
-@pytest.mark.parametrize("lanes", [0, 1, 2, 4])
+@pytest.mark.parametrize("lanes", [0, 1, 2, 4, 8, 16])
 def test_parity_each_lane_layout(torch_cuda, lanes):
     E, T, S, K, dt = 7, 30, 5, 240, 0.005
     mats = synth.audio_materials(8 if lanes == 1 else 16, K / dt)
