@@ -6,7 +6,7 @@ convection, sensor element lag) against closed forms.
   1 / (1 + alpha dt k^2) with k^2 = (pi / (n dx))^2 (m_x^2 + m_y^2 + m_z^2).  Periodic instead of
   mirrored padding, or the wavenumbers of the unpadded grid, fail it.
 - The mean of any field is kept (zero flux), and many steps approach the continuous decay
-  exp(-alpha k^2 t) of the mode.
+  exp(-alpha k^2 t) of the mode; a constant shift of the field commutes with the step.
 - A uniform field loses, per exposed face, dt (eps sigma (T_K^4 - T_amb,K^4) + h (T - T_amb)) /
   (rho c_p dx) in one step (kelvin in the T^4 law, a per-volume rate through the face).
 - The measured reading of a voxel held at T_v follows T_v + (T_0 - T_v) (1 - dt / tau)^k.
@@ -53,6 +53,18 @@ def test_mean_is_kept_and_the_continuum_decay_is_approached():
             F = TS.spectral_diffusion(F, alpha, t / steps, dx)
         errs.append(abs(F[0, 0, 0] / cos_mode(n, (0, 0, 1))[0, 0, 0] - np.exp(-alpha * k2 * t)))
     assert errs[1] < 0.2 * errs[0] and errs[1] < 1e-4
+
+
+def test_a_constant_shift_commutes_with_the_step():
+    """A constant has only the mean mode, which the filter keeps (its k^2 is 0), so shifting the
+    field by a constant before the diffusion and back after changes nothing: the GPU subtracts the
+    ambient temperature before its transforms on this ground."""
+    rng = np.random.default_rng(5)
+    n, dx, alpha, dt = 16, 1e-3, 1e-7, 0.05
+    T = 25.0 + rng.normal(0, 3, (n, n, n))
+    for c in (22.0, -7.5, 300.0):
+        np.testing.assert_allclose(TS.spectral_diffusion(T - c, alpha, dt, dx) + c,
+                                   TS.spectral_diffusion(T, alpha, dt, dx), rtol=0, atol=1e-11)
 
 
 def test_unconditionally_stable():
