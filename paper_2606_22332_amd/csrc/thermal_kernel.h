@@ -181,7 +181,7 @@ __device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const flo
   __syncthreads();
 #pragma unroll
   for (int z = 0; z < n; ++z) col[z] = col[z] - ex[z * PS + y * RS + x];
-  __syncthreads();   // the exchange buffer is free again
+  // (the exchange buffer is written again only after the step's later barrier)
 }
 
 // SPEC = 1: the paper's step (spectral diffusion, T^4 radiation and convection, sensor lag).  Both
@@ -259,14 +259,13 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
     } else {
 #pragma unroll
       for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];
+      __syncthreads();
     }
-    __syncthreads();
-    // 2. clean depth of the link's taxels: the readout's own output when the rollout writes it,
-    //    else recomputed with the readout's FP32 sequence (the same value)
-    if (q.depth) {
-      const float* dep = q.depth + (int64_t)s * ET + (int64_t)e * T + jb;
-      for (int k = tid; k < nl; k += TH_THREADS) cd[k] = th.kappa * dep[k];
-    } else
+    // 2. clean depth of the link's taxels: the readout's own output when the rollout writes it
+    //    (each column reads its own taxels' depths below), else recomputed with the readout's
+    //    FP32 sequence (the same value) into cd
+    const float* dep = q.depth ? q.depth + (int64_t)s * ET + (int64_t)e * T + jb : nullptr;
+    if (!dep) {
     for (int k = tid; k < nl; k += TH_THREADS) {
       const int j = jb + k;
       const float4 ta = p.taxA[j];
@@ -286,16 +285,19 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
       cd[k] = th.kappa * d;
     }
     __syncthreads();
-    // 3. contact coefficient of this column's top voxel, in taxel order
+    }
+    // 3. contact coefficient of this column's top voxel, in taxel order (kappa d per taxel, then
+    //    the sum)
+    auto coef = [&](int k) { return dep ? th.kappa * dep[k] : cd[k]; };
     float cv = 0.f;
     if (nmine <= 4) {
-      if (nmine > 0) cv = cv + cd[mine01 & 0xffffu];
-      if (nmine > 1) cv = cv + cd[mine01 >> 16];
-      if (nmine > 2) cv = cv + cd[mine23 & 0xffffu];
-      if (nmine > 3) cv = cv + cd[mine23 >> 16];
+      if (nmine > 0) cv = cv + coef(mine01 & 0xffffu);
+      if (nmine > 1) cv = cv + coef(mine01 >> 16);
+      if (nmine > 2) cv = cv + coef(mine23 & 0xffffu);
+      if (nmine > 3) cv = cv + coef(mine23 >> 16);
     } else {
       for (int k = 0; k < nl; ++k)
-        if (th.taxel_vox[jb + k] == myvox) cv = cv + cd[k];
+        if (th.taxel_vox[jb + k] == myvox) cv = cv + coef(k);
     }
     if (spec) {
       // 4'. the paper's order after the diffusion: source, contact conduction on the top voxel,
