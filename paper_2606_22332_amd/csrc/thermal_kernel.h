@@ -49,7 +49,7 @@ struct ThermalLaunch {
                                // kernel before this launch), or null: recomputed here
 };
 
-// The paper's spectral diffusion step (App. D.1) on a block held as z-columns `col` (thread (x,y)).
+// The paper's spectral diffusion step (App. D.1) on one 16^3 block.
 // The mirror-padded FFT filter 1 / (1 + a k^2) is diagonal in the DCT-II basis C of the block, with
 // k^2 = (pi / (n dx))^2 (mx^2 + my^2 + mz^2).  It is applied in the equal correction form
 //   T' = T - C3^T (h * C3 (T - T0)),   h = a k^2 / (1 + a k^2) <= a k_max^2,
@@ -134,16 +134,28 @@ __device__ __forceinline__ void dct_axis(float* ex, const DctSplit& A, int base0
     src[(4 * g + 3) * ks] = d.w;
   }
 }
-__device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const float* hk, float T0, float col[TH_N],
-                                                 float* ex, int tid) {
-  constexpr int n = TH_N, RS = TH_N + 1, PS = TH_N * (TH_N + 1);
-  const int x = tid % n, y = tid / n;
+// The step on a block held in the transforms' own layout: lane (g, c) of wave w keeps
+// fv[4 t + r] = T(z = 4 g + r, y = 4 w + t, x = c), which is the forward z pass's B operand and
+// the inverse z pass's D, so those two passes take their operand from registers and give their
+// result back to them: two barriers and a third of the exchange-buffer traffic fewer per step.
+__device__ __forceinline__ void spectral_diffuse_tiles(const DctOperands& C, const float* hk, float T0,
+                                                       float fv[TH_N], float* ex, int tid) {
+  constexpr int RS = TH_N + 1, PS = TH_N * (TH_N + 1);
   const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
+  const dct_acc z0 = {0.f, 0.f, 0.f, 0.f};
+  // forward z: tile t is the plane y = 4 w + t; K = z, columns x
 #pragma unroll
-  for (int z = 0; z < n; ++z) ex[z * PS + y * RS + x] = col[z] - T0;
-  __syncthreads();
-  // forward z: tiles y = 4 w + t; K = z (plane stride), columns x
-  dct_axis(ex, C.fwd, 4 * w * RS, RS, PS, 1, lane);
+  for (int t = 0; t < 4; ++t) {
+    float b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b[r] = fv[4 * t + r] - T0;
+    const dct_acc d = mfma_split(C.fwd, b, z0);
+    float* dst = ex + (4 * w + t) * RS + c;
+    dst[(4 * g + 0) * PS] = d.x;
+    dst[(4 * g + 1) * PS] = d.y;
+    dst[(4 * g + 2) * PS] = d.z;
+    dst[(4 * g + 3) * PS] = d.w;
+  }
   __syncthreads();
   // forward y: planes mz = 4 w + t; K = y (row stride), columns x
   dct_axis(ex, C.fwd, 4 * w * PS, PS, RS, 1, lane);
@@ -156,17 +168,14 @@ __device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const flo
     float b[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) b[r] = pl[c * RS + 4 * g + r];
-    const dct_acc z = {0.f, 0.f, 0.f, 0.f};
-    const dct_acc acc = mfma_split(C.fwd, b, z);
-    // acc: row mx = 4 g + r, column my = c: scaled, it is the inverse's B slice of this lane group
+    const dct_acc acc = mfma_split(C.fwd, b, z0);
     const int b2 = c * c + mz * mz;
     float hb[4];
     hb[0] = acc.x * hk[(4 * g + 0) * (4 * g + 0) + b2];
     hb[1] = acc.y * hk[(4 * g + 1) * (4 * g + 1) + b2];
     hb[2] = acc.z * hk[(4 * g + 2) * (4 * g + 2) + b2];
     hb[3] = acc.w * hk[(4 * g + 3) * (4 * g + 3) + b2];
-    const dct_acc inv = mfma_split(C.inv, hb, z);
-    // inv: row x = 4 g + r, column my = c (every read of the plane is behind it)
+    const dct_acc inv = mfma_split(C.inv, hb, z0);
     pl[c * RS + 4 * g + 0] = inv.x;
     pl[c * RS + 4 * g + 1] = inv.y;
     pl[c * RS + 4 * g + 2] = inv.z;
@@ -176,11 +185,19 @@ __device__ __forceinline__ void spectral_diffuse(const DctOperands& C, const flo
   // inverse y: planes mz = 4 w + t; K = my, columns x
   dct_axis(ex, C.inv, 4 * w * PS, PS, RS, 1, lane);
   __syncthreads();
-  // inverse z: tiles y = 4 w + t; K = mz, columns x
-  dct_axis(ex, C.inv, 4 * w * RS, RS, PS, 1, lane);
-  __syncthreads();
+  // inverse z into the registers: T' = T - correction
 #pragma unroll
-  for (int z = 0; z < n; ++z) col[z] = col[z] - ex[z * PS + y * RS + x];
+  for (int t = 0; t < 4; ++t) {
+    const float* src = ex + (4 * w + t) * RS + c;
+    float b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b[r] = src[(4 * g + r) * PS];
+    const dct_acc d = mfma_split(C.inv, b, z0);
+    fv[4 * t + 0] = fv[4 * t + 0] - d.x;
+    fv[4 * t + 1] = fv[4 * t + 1] - d.y;
+    fv[4 * t + 2] = fv[4 * t + 2] - d.z;
+    fv[4 * t + 3] = fv[4 * t + 3] - d.w;
+  }
   // (the exchange buffer is written again only after the step's later barrier)
 }
 
@@ -200,6 +217,7 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
   __shared__ float ex[n * n * (n + 1)];    // exchange buffer [z][y][x] (rows padded to 17 for the spectral step)
   __shared__ float cd[512];                // kappa * depth per taxel of the link
   __shared__ float top[n * n];
+  __shared__ float cvs[SPEC ? n * n : 1];   // contact coefficient per top voxel (spectral step)
   __shared__ Pose lp, op;
   __shared__ int oid_s;
   // the spectral step's filter correction per |m|^2 and the DCT-II operands of this lane
@@ -211,9 +229,19 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
     __syncthreads();
   }
   float* fld = th.fields + ((int64_t)e * th.F + f) * (n * n * n);
+  // the field in registers: a z-column per thread (x, y), or for the spectral step the transforms'
+  // layout, col[4 t + r] = T(z = 4 g + r, y = 4 w + t, x = c) for lane (g, c) of wave w
+  const int tw = tid >> 6, tg = (tid >> 4) & 3, tc = tid & 15;
   float col[n];
+  if constexpr (SPEC) {
 #pragma unroll
-  for (int z = 0; z < n; ++z) col[z] = fld[(z * n + y) * n + x];
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) col[4 * t + r] = fld[((4 * tg + r) * n + 4 * tw + t) * n + tc];
+  } else {
+#pragma unroll
+    for (int z = 0; z < n; ++z) col[z] = fld[(z * n + y) * n + x];
+  }
   const int jb = __ldg(&p.link_off[l]), je = __ldg(&p.link_off[l + 1]);
   const int nl = je - jb;
   const float Tobj = th.T_obj[e];
@@ -254,37 +282,31 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
       op.p[0] = os[0 * E + e]; op.p[1] = os[1 * E + e]; op.p[2] = os[2 * E + e];
       quat_to_R(os[3 * E + e], os[4 * E + e], os[5 * E + e], os[6 * E + e], op.R);
     }
-    if (spec) {
-      spectral_diffuse(dcto, hks, Tamb, col, ex, tid);
-    } else {
-#pragma unroll
-      for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];
-      __syncthreads();
-    }
     // 2. clean depth of the link's taxels: the readout's own output when the rollout writes it
     //    (each column reads its own taxels' depths below), else recomputed with the readout's
     //    FP32 sequence (the same value) into cd
     const float* dep = q.depth ? q.depth + (int64_t)s * ET + (int64_t)e * T + jb : nullptr;
     if (!dep) {
-    for (int k = tid; k < nl; k += TH_THREADS) {
-      const int j = jb + k;
-      const float4 ta = p.taxA[j];
-      float d = 0.f;
-      const int oid = oid_s;
-      if (oid >= 0 && oid < p.n_obj && ta.w > 0.f) {
-        const float xj[3] = {ta.x, ta.y, ta.z};
-        float qw[3], qo[3];
-        probe_point(lp, q.obj_state ? &op : nullptr, xj, qw, qo);
-        GridHit h;
-        grid_lookup(p.grids[oid], p.grid_vals, qo, h);
-        if (!h.far) {
-          const float diff = ta.w - h.phi;
-          d = diff > 0.f ? diff : 0.f;
+      __syncthreads();   // the poses of this step
+      for (int k = tid; k < nl; k += TH_THREADS) {
+        const int j = jb + k;
+        const float4 ta = p.taxA[j];
+        float d = 0.f;
+        const int oid = oid_s;
+        if (oid >= 0 && oid < p.n_obj && ta.w > 0.f) {
+          const float xj[3] = {ta.x, ta.y, ta.z};
+          float qw[3], qo[3];
+          probe_point(lp, q.obj_state ? &op : nullptr, xj, qw, qo);
+          GridHit h;
+          grid_lookup(p.grids[oid], p.grid_vals, qo, h);
+          if (!h.far) {
+            const float diff = ta.w - h.phi;
+            d = diff > 0.f ? diff : 0.f;
+          }
         }
+        cd[k] = th.kappa * d;
       }
-      cd[k] = th.kappa * d;
-    }
-    __syncthreads();
+      __syncthreads();
     }
     // 3. contact coefficient of this column's top voxel, in taxel order (kappa d per taxel, then
     //    the sum)
@@ -299,44 +321,56 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
       for (int k = 0; k < nl; ++k)
         if (th.taxel_vox[jb + k] == myvox) cv = cv + coef(k);
     }
-    if (spec) {
+    if constexpr (SPEC) {
+      cvs[myvox] = cv;   // read by the lanes holding the top voxels, behind the transforms' barriers
+      spectral_diffuse_tiles(dcto, hks, Tamb, col, ex, tid);
       // 4'. the paper's order after the diffusion: source, contact conduction on the top voxel,
       //     then radiation (T^4 in kelvin, as (T - Ta)(T_K + Ta_K)(T_K^2 + Ta_K^2)) and convection
       //     from every face of the block
       const float TaK = Tamb + 273.15f, TaK2 = TaK * TaK;
 #pragma unroll
-      for (int z = 0; z < n; ++z) {
-        float t = col[z] + g;
-        if (z == n - 1) t = t + cv * (Tobj - t);
-        const int faces = fxy + (z == 0) + (z == n - 1);
-        if (faces) {
-          const float d = t - Tamb, TK = t + 273.15f;
-          const float q4 = d * ((TK + TaK) * fmaf(TK, TK, TaK2));
-          t = t - (float)faces * fmaf(th.k_rad, q4, th.k_conv * d);
+      for (int t = 0; t < 4; ++t) {
+        const int yy = 4 * tw + t;
+        const int fxy_t = (tc == 0) + (tc == n - 1) + (yy == 0) + (yy == n - 1);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int z = 4 * tg + rr;
+          float tv = col[4 * t + rr] + g;
+          if (z == n - 1) tv = tv + cvs[yy * n + tc] * (Tobj - tv);
+          const int faces = fxy_t + (z == 0) + (z == n - 1);
+          if (faces) {
+            const float d = tv - Tamb, TK = tv + 273.15f;
+            const float q4 = d * ((TK + TaK) * fmaf(TK, TK, TaK2));
+            tv = tv - (float)faces * fmaf(th.k_rad, q4, th.k_conv * d);
+          }
+          col[4 * t + rr] = tv;
         }
-        col[z] = t;
+        if (tg == 3) top[yy * n + tc] = col[4 * t + 3];
       }
     } else {
-    // 4. explicit step from the old values (exchange buffer, and registers for z +- 1): the column
-    //    is updated in place from the bottom, with the old value below carried in `below`
-    float below = col[0];
 #pragma unroll
-    for (int z = 0; z < n; ++z) {
-      const float t = col[z];
-      const float* ez = ex + z * n * n;
-      const float xm = ez[sxm], xp = ez[sxp], ym = ez[sym], yp = ez[syp];
-      const float zm = z > 0 ? below : t;
-      const float zp = z < n - 1 ? col[z + 1] : t;
-      const float sum = ((xm + xp) + (ym + yp)) + (zm + zp);
-      const int faces = fxy + (z == 0) + (z == n - 1);
-      const float rfx = rf * (float)faces;
-      float src = g + rfx * (Tamb - t);
-      if (z == n - 1) src = src + cv * (Tobj - t);
-      below = t;
-      col[z] = t + (r * (sum - 6.0f * t) + src);
+      for (int z = 0; z < n; ++z) ex[(z * n + y) * n + x] = col[z];
+      __syncthreads();
+      // 4. explicit step from the old values (exchange buffer, and registers for z +- 1): the
+      //    column is updated in place from the bottom, with the old value below carried in `below`
+      float below = col[0];
+#pragma unroll
+      for (int z = 0; z < n; ++z) {
+        const float t = col[z];
+        const float* ez = ex + z * n * n;
+        const float xm = ez[sxm], xp = ez[sxp], ym = ez[sym], yp = ez[syp];
+        const float zm = z > 0 ? below : t;
+        const float zp = z < n - 1 ? col[z + 1] : t;
+        const float sum = ((xm + xp) + (ym + yp)) + (zm + zp);
+        const int faces = fxy + (z == 0) + (z == n - 1);
+        const float rfx = rf * (float)faces;
+        float src = g + rfx * (Tamb - t);
+        if (z == n - 1) src = src + cv * (Tobj - t);
+        below = t;
+        col[z] = t + (r * (sum - 6.0f * t) + src);
+      }
+      top[myvox] = col[n - 1];
     }
-    }
-    top[myvox] = col[n - 1];
     __syncthreads();   // every read of ex and cd is done; top is complete
     if (spec && th.lag > 0.f && tid < nl) tm = fmaf(th.lag, top[tvox] - tm, tm);
     if (q.temperature) {
@@ -348,8 +382,15 @@ __global__ __launch_bounds__(TH_THREADS, 4) void tg_thermal_kernel(const Thermal
           if (th.taxel_vox[j] < 0) out[j] = 0.f;
     }
   }
+  if constexpr (SPEC) {
 #pragma unroll
-  for (int z = 0; z < n; ++z) fld[(z * n + y) * n + x] = col[z];
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) fld[((4 * tg + r) * n + 4 * tw + t) * n + tc] = col[4 * t + r];
+  } else {
+#pragma unroll
+    for (int z = 0; z < n; ++z) fld[(z * n + y) * n + x] = col[z];
+  }
   if (spec && th.lag > 0.f && tid < nl) th.t_meas[(int64_t)e * T + jb + tid] = tm;
 }
 
