@@ -1,6 +1,6 @@
 // Contact-audio modal synthesis (App. E, contact audio) behind include/tg_audio.h.
 //
-// Work layout.  G lanes (1, 2 or 4) serve one (env, sensor link) pair and hold its bank's slots
+// Work layout.  G lanes (1, 2, 4, 8 or 16) serve one (env, sensor link) pair and hold its bank's slots
 // between them: MPL resonators per lane, states and coefficients in FP64 registers.  A wave holds
 // 64 / G pairs and runs every step of the launch.  Per step:
 //   1. excitation: the pair's lanes stride over the link's taxels, form f . m and
@@ -94,8 +94,6 @@ __device__ __forceinline__ double bank_part(double u, const double* a1, const do
   }
   return part;
 }
-// G samples' parts p[0..G) in each lane of a pair -> lane sub gets the pair's s[k0 + sub]: a
-// transposed reduction, each exchange sending half of what the lane still holds.
 // Stage with bit `bit` of the partner: of the n values q[] (samples indexed by the bits not yet
 // reduced), keep the half whose bit matches the lane's and add the partner's copy of it.
 template <int N, int BIT>
@@ -112,6 +110,8 @@ __device__ __forceinline__ void transpose_stage(double* q, int sub) {
     q[i] = keep + other;
   }
 }
+// G samples' parts p[0..G) in each lane of a pair -> lane sub gets the pair's s[k0 + sub]: a
+// transposed reduction, each exchange sending half of what the lane still holds.
 template <int G>
 __device__ __forceinline__ double group_transpose_sum(const double* p, int sub) {
   if constexpr (G == 1) {
