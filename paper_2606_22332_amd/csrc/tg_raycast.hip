@@ -77,41 +77,35 @@ __device__ __forceinline__ float dot3f(float ax, float ay, float az, float bx, f
   return fmaf(az, bz, fmaf(ay, by, ax * bx));
 }
 // squared distance from p to the closest point of triangle (a, b, c); face: whether that point
-// lies inside the face (not on an edge or vertex)
+// lies inside the face (not on an edge or vertex).  The Voronoi region of the point (Ericson's
+// tests, in his order of precedence) picks the closest point as a + v (b - a) + w (c - a) with
+// v = nv / den and w = nw / den; the regions are selected without branches, so the lanes of a
+// wave, whose probes fall in different regions, do not diverge, and one reciprocal serves them all.
 __device__ float tri_dist2(float px, float py, float pz, const float4& a, const float4& b, const float4& c, bool& face) {
-  face = false;
   const float abx = b.x - a.x, aby = b.y - a.y, abz = b.z - a.z;
   const float acx = c.x - a.x, acy = c.y - a.y, acz = c.z - a.z;
   const float apx = px - a.x, apy = py - a.y, apz = pz - a.z;
-  float qx, qy, qz;
   const float d1 = dot3f(abx, aby, abz, apx, apy, apz), d2 = dot3f(acx, acy, acz, apx, apy, apz);
   const float bpx = px - b.x, bpy = py - b.y, bpz = pz - b.z;
   const float d3 = dot3f(abx, aby, abz, bpx, bpy, bpz), d4 = dot3f(acx, acy, acz, bpx, bpy, bpz);
   const float cpx = px - c.x, cpy = py - c.y, cpz = pz - c.z;
   const float d5 = dot3f(abx, aby, abz, cpx, cpy, cpz), d6 = dot3f(acx, acy, acz, cpx, cpy, cpz);
   const float vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
-  if (d1 <= 0.f && d2 <= 0.f) {                       // vertex a
-    qx = a.x; qy = a.y; qz = a.z;
-  } else if (d3 >= 0.f && d4 <= d3) {                 // vertex b
-    qx = b.x; qy = b.y; qz = b.z;
-  } else if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) {   // edge ab
-    const float v = d1 * __builtin_amdgcn_rcpf(d1 - d3);
-    qx = fmaf(v, abx, a.x); qy = fmaf(v, aby, a.y); qz = fmaf(v, abz, a.z);
-  } else if (d6 >= 0.f && d5 <= d6) {                 // vertex c
-    qx = c.x; qy = c.y; qz = c.z;
-  } else if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) {   // edge ac
-    const float w = d2 * __builtin_amdgcn_rcpf(d2 - d6);
-    qx = fmaf(w, acx, a.x); qy = fmaf(w, acy, a.y); qz = fmaf(w, acz, a.z);
-  } else if (va <= 0.f && (d4 - d3) >= 0.f && (d5 - d6) >= 0.f) {   // edge bc
-    const float w = (d4 - d3) * __builtin_amdgcn_rcpf((d4 - d3) + (d5 - d6));
-    qx = fmaf(w, c.x - b.x, b.x); qy = fmaf(w, c.y - b.y, b.y); qz = fmaf(w, c.z - b.z, b.z);
-  } else {                                            // face
-    face = true;
-    const float den = __builtin_amdgcn_rcpf(va + vb + vc), v = vb * den, w = vc * den;
-    qx = fmaf(w, acx, fmaf(v, abx, a.x));
-    qy = fmaf(w, acy, fmaf(v, aby, a.y));
-    qz = fmaf(w, acz, fmaf(v, abz, a.z));
-  }
+  const float e43 = d4 - d3, e56 = d5 - d6;
+  // lowest precedence first: the face, then edge bc, edge ac, vertex c, edge ab, vertex b, vertex a
+  float nv = vb, nw = vc, den = va + vb + vc;
+  bool f = true;
+  if (va <= 0.f && e43 >= 0.f && e56 >= 0.f) { nv = e56; nw = e43; den = e43 + e56; f = false; }   // edge bc
+  if (vb <= 0.f && d2 >= 0.f && d6 <= 0.f) { nv = 0.f; nw = d2; den = d2 - d6; f = false; }        // edge ac
+  if (d6 >= 0.f && d5 <= d6) { nv = 0.f; nw = 1.f; den = 1.f; f = false; }                        // vertex c
+  if (vc <= 0.f && d1 >= 0.f && d3 <= 0.f) { nv = d1; nw = 0.f; den = d1 - d3; f = false; }        // edge ab
+  if (d3 >= 0.f && d4 <= d3) { nv = 1.f; nw = 0.f; den = 1.f; f = false; }                        // vertex b
+  if (d1 <= 0.f && d2 <= 0.f) { nv = 0.f; nw = 0.f; den = 1.f; f = false; }                       // vertex a
+  face = f;
+  const float inv = __builtin_amdgcn_rcpf(den), v = nv * inv, w = nw * inv;
+  const float qx = fmaf(w, acx, fmaf(v, abx, a.x));
+  const float qy = fmaf(w, acy, fmaf(v, aby, a.y));
+  const float qz = fmaf(w, acz, fmaf(v, abz, a.z));
   const float dx = px - qx, dy = py - qy, dz = pz - qz;
   return dot3f(dx, dy, dz, dx, dy, dz);
 }
