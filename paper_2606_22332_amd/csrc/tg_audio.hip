@@ -135,6 +135,7 @@ template <int G, int MPL>
 __global__ __launch_bounds__(64) void tg_audio_kernel(const AudioParams p, const AudioLaunch q) {
   constexpr int PAIRS = 64 / G;
   extern __shared__ float rows[];   // [PAIRS][KP]
+  __shared__ double red[G == 8 ? PAIRS * G * (G + 1) : 1];   // [pair][sample][lane] parts (rows padded)
   const int lane = threadIdx.x;
   const int pr = lane / G, sub = lane % G;
   const int64_t EL = (int64_t)p.E * p.Ls;
@@ -218,7 +219,20 @@ __global__ __launch_bounds__(64) void tg_audio_kernel(const AudioParams p, const
         pk[i] = bank_part<MPL>(fma(amp, (double)xc[i], extra), a1, a2n, gg, y1, y2);
         extra = 0.0;
       }
-      row[k0 + sub] = (float)group_transpose_sum<G>(pk, sub);
+      if constexpr (G == 8) {
+        // the G parts of each sample through LDS: lane sub adds sample sub's parts in lane order
+        // (one wave: its LDS writes land before its later reads).  At 8 lanes this beats the seven
+        // DPP exchanges per 8 samples; at 16 the LDS bank conflicts make it slower, at 4 it ties.
+        double* rd = red + pr * G * (G + 1);
+#pragma unroll
+        for (int i = 0; i < G; ++i) rd[i * (G + 1) + sub] = pk[i];
+        double acc = rd[sub * (G + 1)];
+#pragma unroll
+        for (int ll = 1; ll < G; ++ll) acc += rd[sub * (G + 1) + ll];
+        row[k0 + sub] = (float)acc;
+      } else {
+        row[k0 + sub] = (float)group_transpose_sum<G>(pk, sub);
+      }
     }
     for (int k = KG; k < K; ++k) {
       const double v = group_sum<G>(bank_part<MPL>(fma(amp, (double)row[k], extra), a1, a2n, gg, y1, y2));
